@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Throughput of the fast BTTB products on one MI355X.
+
+One step = one forward product d = G m plus one transpose product G^T r on the
+gravity volume of 1000 x 1000 stations, 12 padding cells per side
+(1024 x 1024 x 128 prisms of 25 x 25 x 20 m), spectra precomputed (their
+generation is timed separately), inputs resident in HBM.  The metric is model
+cells per second: nx * ny * nz / (time of one step).
+
+Prints one JSON line.  Besides the headline FP32 number it reports the FP64
+path, the kernel-generation time, per-kernel times from HIP events recorded on
+the launch stream, the roofline of the dominant kernel, and the CPU oracle's
+rate on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+METRIC = "model cells/s for G·m+Gᵀ·r, FP32 vs FP64 GPU at rel L2≤2e-5; HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+KERNELS_FWD = ["fwd_rows_r2c", "fwd_cols_fft_mac", "fwd_rows_c2r"]
+KERNELS_TR = ["tr_rows_r2c", "tr_cols_fft_mac", "tr_rows_c2r"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(pr, Nx, Ny, esz, nrhs=1):
+    """Algorithmic HBM bytes per launch of each kernel of the two products:
+    compulsory reads and writes of its inputs, outputs and spectra."""
+    nx, ny, nz = W.dims(pr)
+    sx, sy = pr["sx"], pr["sy"]
+    nc = Nx // 2 + 1
+    c = 2 * esz
+    spec = nz * nc * Ny * c
+    return {
+        "fwd_rows_r2c": nrhs * nz * (ny * nx * esz + nc * ny * c),
+        "fwd_cols_fft_mac": spec + nrhs * (nz * nc * ny * c + nc * sy * c),
+        "fwd_rows_c2r": nrhs * (nc * sy * c + sy * sx * esz),
+        "tr_rows_r2c": nrhs * (sy * sx * esz + nc * sy * c),
+        "tr_cols_fft_mac": spec + nrhs * (nc * sy * c + nz * nc * ny * c),
+        "tr_rows_c2r": nrhs * nz * (nc * ny * c + ny * nx * esz),
+    }
+
+
+def pair_bytes(pr, Nx, Ny, esz):
+    """Algorithmic bytes of one G m + G^T r pair: read m, spectra twice,
+    write G^T r, read r, write d."""
+    nx, ny, nz = W.dims(pr)
+    sx, sy = pr["sx"], pr["sy"]
+    spec = nz * (Nx // 2 + 1) * Ny * 2 * esz
+    return 2 * spec + 2 * nx * ny * nz * esz + 2 * sx * sy * esz
+
+
+def run_gpu(torch, B, pr, prec, m_host, r_host, steps, warmup, want_kernels=True):
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    plan = B.Plan(pr, prec)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    plan.generate()
+    e1.record(s)
+    torch.cuda.synchronize()
+    gen_ms = e0.elapsed_time(e1)
+    m = torch.from_numpy(m_host).to(device="cuda", dtype=dt)
+    r = torch.from_numpy(r_host).to(device="cuda", dtype=dt)
+    d = torch.empty((pr["sy"], pr["sx"]), dtype=dt, device="cuda")
+    mt = torch.empty_like(m)
+    ws = plan.workspace(1)
+    for _ in range(warmup):
+        plan.forward(m, out=d)
+        plan.transpose(r, out=mt)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(steps):
+        plan.forward(m, out=d)
+        plan.transpose(r, out=mt)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    kern = None
+    if want_kernels:
+        acc = np.zeros(6)
+        for _ in range(steps):
+            f = B.bttb_forward_profiled(plan.handle, plan.spectra, m, d, 1, ws)
+            t = B.bttb_transpose_profiled(plan.handle, plan.spectra, r, mt, 1, ws)
+            acc += np.array(f + t)
+        kern = dict(zip(KERNELS_FWD + KERNELS_TR, (acc / steps).tolist()))
+    out = dict(plan=plan, ms=ms, gen_ms=gen_ms, kernels=kern, d=d, mt=mt, m=m, r=r)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-stations", type=int, default=6)
+    ap.add_argument("--cpu-prisms", type=int, default=48)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the product is not sharded across GPUs); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1912_06976_amd as B
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+
+    pr = W.gravity_1024()
+    nx, ny, nz = W.dims(pr)
+    cells = nx * ny * nz
+    log("inputs: ellipsoid model and N(0,1) data, seeds 301 / 302")
+    m64 = W.ellipsoid_model(pr, 301)
+    r64 = W.normal_data(pr, 302)
+
+    log("fp32 run")
+    g32 = run_gpu(torch, B, pr, "fp32", m64.astype(np.float32), r64.astype(np.float32), args.steps,
+                  args.warmup)
+    Nx, Ny = g32["plan"].nx_fft, g32["plan"].ny_fft
+    ms = g32["ms"]
+    value = cells / (ms * 1e-3)
+    kb = kernel_bytes(pr, Nx, Ny, 4)
+    kern = g32["kernels"]
+    dom = max(kern, key=kern.get)
+    ach = kb[dom] / (kern[dom] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes": kb[dom], "avg_ms": round(kern[dom], 4)}
+    pb = pair_bytes(pr, Nx, Ny, 4)
+    result = {
+        "metric": METRIC, "value": value, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "gravity g_z 1000x1000 stations, 12-cell padding -> 1024x1024x128 prisms "
+                               "of 25x25x20 m, 20 random ellipsoids; one G*m + one G^T*r",
+                   "fft": "%dx%d" % (Nx, Ny), "nrhs": 1, "precision": "fp32 spectra/FFT/MAC, fp64 generator",
+                   "accumulation": "fp64 depth accumulator"},
+        "roofline": roof,
+        "step_algorithmic_GBps": round(pb / (ms * 1e-3) / 1e9, 1),
+        "step_algorithmic_bytes": pb,
+        "kernel_ms": {k: round(v, 4) for k, v in kern.items()},
+        "generate_ms": round(g32["gen_ms"], 2),
+    }
+
+    # sampled stations / prisms for the oracle (CPU baseline and parity sample)
+    d32 = g32["d"].double().cpu().numpy()
+    mt32 = g32["mt"].double().cpu().numpy()
+    if not args.no_fp64:
+        log("fp64 run")
+        del g32
+        torch.cuda.empty_cache()
+        g64 = run_gpu(torch, B, pr, "fp64", m64, r64, max(3, args.steps // 2), 2, want_kernels=False)
+        result["fp64"] = {"ms_per_step": g64["ms"], "value": cells / (g64["ms"] * 1e-3),
+                          "generate_ms": round(g64["gen_ms"], 2)}
+        result["speedup_fp32_vs_fp64"] = round(g64["ms"] / ms, 3)
+        d64 = g64["d"].cpu().numpy()
+        mt64 = g64["mt"].cpu().numpy()
+        result["fp32_vs_fp64_rel_l2"] = {
+            "forward": float(np.linalg.norm(d32 - d64) / np.linalg.norm(d64)),
+            "transpose": float(np.linalg.norm(mt32 - mt64) / np.linalg.norm(mt64))}
+        del g64
+        torch.cuda.empty_cache()
+
+    if not args.no_cpu_baseline:
+        import oracle
+        P = oracle.problem_from_dict(pr)
+        st = [(int(i), int(j)) for i, j in zip(W.sample_indices(903, args.cpu_stations, pr["sx"]),
+                                               W.sample_indices(904, args.cpu_stations, pr["sy"]))]
+        pq = np.stack([W.sample_indices(905, args.cpu_prisms, nx), W.sample_indices(906, args.cpu_prisms, ny),
+                       np.random.default_rng(907).integers(0, nz, size=args.cpu_prisms)], axis=1)
+        oracle.build()
+        log("cpu oracle sample: %d stations, %d prisms" % (len(st), len(pq)))
+        t0 = time.perf_counter()
+        ds = oracle.station_sums(P, m64, st)
+        t1 = time.perf_counter()
+        ts = oracle.prism_sums(P, r64, pq)
+        t2 = time.perf_counter()
+        per_st = (t1 - t0) / len(st)
+        per_pr = (t2 - t1) / len(pq)
+        t_pair = per_st * pr["sx"] * pr["sy"] + per_pr * cells
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+        threads = min(threads, len(os.sched_getaffinity(0)))
+        result["cpu_baseline"] = {
+            "value": cells / t_pair, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "sample": "direct sums (no FFT) of G m at %d stations and G^T r at %d prisms of the same "
+                      "workload, %.1f s, extrapolated to one full G m + G^T r" % (len(st), len(pq), t2 - t0)}
+        gi = np.array([d32[j, i] for (i, j) in st])
+        gt = np.array([mt32[r, q, p] for (p, q, r) in pq])
+        result["parity_sample_rel_l2"] = {
+            "forward": float(np.linalg.norm(gi - ds) / np.linalg.norm(ds)),
+            "transpose": float(np.linalg.norm(gt - ts) / np.linalg.norm(ts))}
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,177 @@
+/*
+ * bttb.h -- C ABI of the gfx950 fast BTTB product library (libbttb.so).
+ *
+ * Forward and transpose products with the 3-D gravity (g_z) and magnetic
+ * total-field-anomaly sensitivity matrices of Hogue, Renaut & Vatankhah,
+ * "A Tutorial and Open Source Software for the Efficient Evaluation of
+ * Gravity and Magnetic Kernels" (arXiv 1912.06976):
+ *
+ *   d = G m = sum_r G^(r) m_r,     G^T r = [G^(1)^T r; ...; G^(nz)^T r]
+ *   (Sec. 2, eq. Gslice; Sec. 5, the depth-layer split),
+ *
+ * where each depth-layer block G^(r) is block-Toeplitz with Toeplitz blocks
+ * (symmetric for gravity without padding, non-symmetric for the magnetic
+ * kernel; Sec. 2.2), embedded in a block-circulant matrix whose generator
+ * T_r (Sec. 3, eq. Tcircpadded / eq. Tcircpaddedgeneral) is transformed once
+ * with a 2-D FFT; the products are then pointwise multiplications in the
+ * Fourier domain (Sec. 3, eq. GrviaT), accumulated over depth before one
+ * inverse 2-D FFT for the forward product.
+ *
+ * Conventions (0-based; the paper's 1-based indices shifted by one):
+ *   station (i, j), i < sx, j < sy, at ((i + 1/2) dx, (j + 1/2) dy, -h);
+ *   prism (p, q, r), p < nx = sx + pxl + pxr, q < ny = sy + pyl + pyr,
+ *   r < nz, spans [(p - pxl) dx, (p - pxl + 1) dx] x
+ *   [(q - pyl) dy, (q - pyl + 1) dy] x [z_r, z_{r+1}], z pointing down
+ *   (Sec. 2.1.2 and the coordinate table of the appendix);
+ *   G[k][l] with k = j sx + i and l = r nx ny + q nx + p (Sec. 2, eq. htilde).
+ *
+ * Memory layouts (x fastest everywhere):
+ *   model m, transpose output mt:   [nrhs][nz][ny][nx]
+ *   data d, transpose input r:      [nrhs][sy][sx]
+ *   all in the plan's precision (float for BTTB_FP32, double for BTTB_FP64).
+ *
+ * Ownership: the plan is a host object owned by the caller.  All device
+ * memory (spectra, workspace, inputs, outputs) is allocated and owned by the
+ * caller; the library never allocates device memory and never synchronises
+ * the stream (except bttb_debug_generator, a test hook).  Device calls only
+ * enqueue work on the given stream (a hipStream_t passed as void*, NULL =
+ * the default stream) and return; asynchronous faults surface at the
+ * caller's next synchronisation.  Invalid arguments are rejected before
+ * anything is enqueued, with a status code and a thread-local message
+ * (bttb_last_error).  No C++ exception crosses this interface.
+ *
+ * Thread safety: a plan is immutable after creation; concurrent calls on one
+ * plan are safe if each uses its own workspace.
+ */
+#ifndef BTTB_H
+#define BTTB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BTTB_OK = 0,
+    BTTB_ERR_INVALID_VALUE = 1,      /* a descriptor field or argument is out of range  */
+    BTTB_ERR_NULL_POINTER = 2,       /* a required pointer is NULL                      */
+    BTTB_ERR_UNSUPPORTED = 3,        /* valid but not supported (e.g. FFT length > 4096) */
+    BTTB_ERR_WORKSPACE_TOO_SMALL = 4,/* ws_bytes below what bttb_plan_query reports     */
+    BTTB_ERR_HIP = 5,                /* a HIP launch or runtime call failed             */
+    BTTB_ERR_INTERNAL = 6
+} bttb_status;
+
+typedef enum {
+    BTTB_GRAVITY_GZ = 0,   /* vertical gravity, mGal per (g/cm^3) (Sec. 4.1)           */
+    BTTB_MAGNETIC_TMI = 1, /* total-field anomaly of induced magnetisation, nT per SI
+                              susceptibility (Sec. 4.2)                                */
+    BTTB_PROBE = 99        /* test hook: entry = dx + 4096 dy + 2^24 r for the cell
+                              offsets dx = p - pxl - i, dy = q - pyl - j               */
+} bttb_problem;
+
+typedef enum { BTTB_FP32 = 0, BTTB_FP64 = 1 } bttb_precision;
+
+/* Depth accumulation of the FP32 forward product (ignored for FP64):
+ * BTTB_ACC_WIDE accumulates the per-layer products in FP64 (default),
+ * BTTB_ACC_TWOSUM uses compensated FP32 (TwoSum) accumulation,
+ * BTTB_ACC_PLAIN plain FP32 sums. */
+typedef enum { BTTB_ACC_DEFAULT = 0, BTTB_ACC_PLAIN = 1, BTTB_ACC_TWOSUM = 2, BTTB_ACC_WIDE = 3 } bttb_accumulation;
+
+/*
+ * Problem description: the parameter set of the paper's Table 2
+ * (prob_params, gsx/gsy/gsz, z_blocks, I, D, F).
+ */
+typedef struct {
+    int32_t problem;           /* bttb_problem                                         */
+    int32_t precision;         /* bttb_precision of spectra, inputs and outputs        */
+    int32_t nx, ny, nz;        /* prism grid; nx, ny must equal sx + pxl + pxr, sy + pyl + pyr
+                                  (0: derived); nz >= 1                                */
+    int32_t sx, sy;            /* station grid, >= 1                                   */
+    int32_t pxl, pxr, pyl, pyr;/* padding prisms left/right in x and y, >= 0           */
+    double dx, dy, dz;         /* cell sizes [m], > 0; dz unused if z_edges != NULL    */
+    const double* z_edges;     /* optional host array of nz + 1 strictly increasing
+                                  depths [m], z_edges[0] >= 0; copied at creation     */
+    double station_height;     /* h >= 0: stations at z = -h (z down)                  */
+    double inclination_deg;    /* magnetic field inclination I in [-90, 90]            */
+    double declination_deg;    /* declination D from +x (North) towards +y (East)      */
+    double field_nT;           /* field intensity F [nT], > 0 for BTTB_MAGNETIC_TMI    */
+    double scale;              /* 0: default (6.6743e-3 mGal per (g/cm^3 m) for gravity,
+                                  F / (4 pi) for the magnetic kernel, 1 for the probe) */
+    int32_t nx_fft, ny_fft;    /* 0: smallest power of two >= max(8, s + n - 1); else a
+                                  power of two in [max(8, s + n - 1), 4096]            */
+    int32_t accumulation;      /* bttb_accumulation                                    */
+} bttb_problem_desc;
+
+typedef struct bttb_plan_s* bttb_plan_t;
+
+/* Validate the descriptor and build a host-only plan (no device work).
+ * Errors: NULL_POINTER, INVALID_VALUE, UNSUPPORTED. */
+bttb_status bttb_plan_create(const bttb_problem_desc* desc, bttb_plan_t* out);
+
+/* Release a plan (NULL is accepted). */
+bttb_status bttb_plan_destroy(bttb_plan_t plan);
+
+/* Sizes: spectra_bytes for the opaque spectra buffer; workspace_bytes that
+ * suffices for bttb_kernel_generate and for bttb_forward / bttb_transpose
+ * with up to nrhs right-hand sides; the chosen FFT lengths.  Any output
+ * pointer may be NULL.  Errors: NULL_POINTER (plan), INVALID_VALUE (nrhs < 1). */
+bttb_status bttb_plan_query(bttb_plan_t plan, int32_t nrhs, size_t* spectra_bytes,
+                            size_t* workspace_bytes, int32_t* nx_fft, int32_t* ny_fft);
+
+/* Fill the caller's spectra buffer (device, spectra_bytes, 256-byte aligned):
+ * the generator T_r of every layer is evaluated in FP64 from the closed-form
+ * prism integrals (Sec. 4.1 Algorithm gravity, Sec. 4.2 Algorithm magnetic),
+ * placed in the circulant (Sec. 3, eq. Tcircpadded / Tcircpaddedgeneral),
+ * transformed with an FP64 2-D FFT, scaled by 1 / (Nx Ny) and rounded to the
+ * plan precision (the transform of the paper's sym_BTTBFFT / BTTBFFT).  The
+ * transpose uses the conjugate of the same spectra (for a real generator
+ * the transform of the flipped generator of eq. Ttran is the conjugate).
+ * workspace: device, >= workspace_bytes of bttb_plan_query(plan, 1, ...). */
+bttb_status bttb_kernel_generate(bttb_plan_t plan, void* spectra, void* workspace,
+                                 size_t ws_bytes, void* stream);
+
+/* d = G m for nrhs right-hand sides (the paper's mult_BTTB with t = 1).
+ * m: device [nrhs][nz][ny][nx]; d: device [nrhs][sy][sx]; workspace >=
+ * workspace_bytes of bttb_plan_query(plan, nrhs, ...).  m and d must not
+ * overlap the workspace.  Errors: NULL_POINTER, INVALID_VALUE (nrhs < 1),
+ * WORKSPACE_TOO_SMALL, HIP. */
+bttb_status bttb_forward(bttb_plan_t plan, const void* spectra, const void* m, void* d,
+                         int32_t nrhs, void* workspace, size_t ws_bytes, void* stream);
+
+/* mt = G^T r for nrhs right-hand sides (mult_BTTB with t = 2).
+ * r: device [nrhs][sy][sx]; mt: device [nrhs][nz][ny][nx]. */
+bttb_status bttb_transpose(bttb_plan_t plan, const void* spectra, const void* r, void* mt,
+                           int32_t nrhs, void* workspace, size_t ws_bytes, void* stream);
+
+/* Profiling hooks: the same work as bttb_forward / bttb_transpose, with HIP
+ * events recorded on the stream around each of the three kernels (row
+ * transform, column transform with the depth multiply-accumulate, output row
+ * transform); waits for the events and stores the three kernel durations in
+ * milliseconds in kernel_ms[0..2].  Synchronises the stream. */
+bttb_status bttb_forward_profiled(bttb_plan_t plan, const void* spectra, const void* m, void* d,
+                                  int32_t nrhs, void* workspace, size_t ws_bytes, void* stream,
+                                  float* kernel_ms);
+bttb_status bttb_transpose_profiled(bttb_plan_t plan, const void* spectra, const void* r, void* mt,
+                                    int32_t nrhs, void* workspace, size_t ws_bytes, void* stream,
+                                    float* kernel_ms);
+
+/* Test hook: evaluate the FP64 circulant generator T_r of one layer into the
+ * workspace and copy it to host_out ([ny_fft][nx_fft] doubles, x fastest).
+ * Synchronises the stream.  Errors: NULL_POINTER, INVALID_VALUE (layer out
+ * of range), WORKSPACE_TOO_SMALL, HIP. */
+bttb_status bttb_debug_generator(bttb_plan_t plan, int32_t layer, double* host_out,
+                                 void* workspace, size_t ws_bytes, void* stream);
+
+/* Static description of a status code. */
+const char* bttb_status_string(bttb_status s);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* bttb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BTTB_H */

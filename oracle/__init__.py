@@ -168,6 +168,15 @@ class Problem:
                         self.effective_scale())
 
 
+def problem_from_dict(pr: dict) -> Problem:
+    """Problem from a plain description dict (keys as in workloads.problem)."""
+    kind = {"gravity": GRAVITY, "magnetic": MAGNETIC, "probe": PROBE}[pr["kind"]]
+    return Problem(kind=kind, sx=pr["sx"], sy=pr["sy"], nz=pr["nz"], pxl=pr["pxl"], pxr=pr["pxr"],
+                   pyl=pr["pyl"], pyr=pr["pyr"], dx=pr["dx"], dy=pr["dy"], dz=pr["dz"],
+                   z_edges=pr["z_edges"], h=pr["h"], incl=pr["incl"], decl=pr["decl"],
+                   field_nT=pr["field_nT"], scale=pr["scale"])
+
+
 def prism_value(kind: int, b, incl: float = 90.0, decl: float = 0.0, scale: float = 1.0,
                 quad: bool = False):
     """scale * signed 8-corner sum for one prism b = (chi1, chi2, ups1, ups2, zeta1, zeta2)

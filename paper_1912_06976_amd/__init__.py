@@ -1,0 +1,15 @@
+"""Fast BTTB forward / transpose products with 3-D gravity and magnetic kernels
+on AMD Instinct MI355X (gfx950).
+
+The products d = G m and G^T r of Hogue, Renaut & Vatankhah (arXiv
+1912.06976) run in hand-written HIP kernels behind the C ABI of
+``include/bttb.h`` (libbttb.so); this package is its Python binding.
+"""
+from ._lib import BttbError, EXPORTS, LIB_PATH, load  # noqa: F401
+from .plan import (Plan, bttb_debug_generator, bttb_forward, bttb_forward_profiled,  # noqa: F401
+                   bttb_kernel_generate, bttb_plan_create, bttb_plan_destroy, bttb_plan_query,
+                   bttb_transpose, bttb_transpose_profiled)
+
+__all__ = ["Plan", "BttbError", "bttb_plan_create", "bttb_plan_destroy", "bttb_plan_query",
+           "bttb_kernel_generate", "bttb_forward", "bttb_transpose", "bttb_forward_profiled",
+           "bttb_transpose_profiled", "bttb_debug_generator", "load"]

@@ -1,0 +1,84 @@
+"""ctypes declarations of the C ABI in include/bttb.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbttb.so")
+
+BTTB_OK = 0
+STATUS_NAMES = {0: "BTTB_OK", 1: "BTTB_ERR_INVALID_VALUE", 2: "BTTB_ERR_NULL_POINTER",
+                3: "BTTB_ERR_UNSUPPORTED", 4: "BTTB_ERR_WORKSPACE_TOO_SMALL", 5: "BTTB_ERR_HIP",
+                6: "BTTB_ERR_INTERNAL"}
+BTTB_GRAVITY_GZ, BTTB_MAGNETIC_TMI, BTTB_PROBE = 0, 1, 99
+BTTB_FP32, BTTB_FP64 = 0, 1
+BTTB_ACC_DEFAULT, BTTB_ACC_PLAIN, BTTB_ACC_TWOSUM, BTTB_ACC_WIDE = 0, 1, 2, 3
+
+#: every symbol include/bttb.h declares
+EXPORTS = ["bttb_plan_create", "bttb_plan_destroy", "bttb_plan_query", "bttb_kernel_generate",
+           "bttb_forward", "bttb_transpose", "bttb_forward_profiled", "bttb_transpose_profiled",
+           "bttb_debug_generator", "bttb_status_string", "bttb_last_error"]
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [
+        ("problem", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("sx", ctypes.c_int32), ("sy", ctypes.c_int32),
+        ("pxl", ctypes.c_int32), ("pxr", ctypes.c_int32), ("pyl", ctypes.c_int32), ("pyr", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+        ("z_edges", ctypes.POINTER(ctypes.c_double)),
+        ("station_height", ctypes.c_double),
+        ("inclination_deg", ctypes.c_double), ("declination_deg", ctypes.c_double),
+        ("field_nT", ctypes.c_double), ("scale", ctypes.c_double),
+        ("nx_fft", ctypes.c_int32), ("ny_fft", ctypes.c_int32),
+        ("accumulation", ctypes.c_int32),
+    ]
+
+
+class BttbError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        self.status = status
+        super().__init__("%s failed: %s (%s)" % (fn, STATUS_NAMES.get(status, status), msg))
+
+
+_handle = None
+
+
+def load(path: str | None = None) -> ctypes.CDLL:
+    """Load libbttb.so; raises if it has not been built (no fallback exists)."""
+    global _handle
+    if _handle is not None:
+        return _handle
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError("libbttb.so is not built (%s); run python -m paper_1912_06976_amd.build" % p)
+    L = ctypes.CDLL(p)
+    vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
+    L.bttb_plan_create.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(vp)]
+    L.bttb_plan_destroy.argtypes = [vp]
+    L.bttb_plan_query.argtypes = [vp, i32, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(i32),
+                                  ctypes.POINTER(i32)]
+    L.bttb_kernel_generate.argtypes = [vp, vp, vp, sz, vp]
+    L.bttb_forward.argtypes = [vp, vp, vp, vp, i32, vp, sz, vp]
+    L.bttb_transpose.argtypes = [vp, vp, vp, vp, i32, vp, sz, vp]
+    L.bttb_forward_profiled.argtypes = [vp, vp, vp, vp, i32, vp, sz, vp, ctypes.POINTER(ctypes.c_float)]
+    L.bttb_transpose_profiled.argtypes = [vp, vp, vp, vp, i32, vp, sz, vp, ctypes.POINTER(ctypes.c_float)]
+    L.bttb_debug_generator.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), vp, sz, vp]
+    L.bttb_status_string.argtypes = [ctypes.c_int]
+    L.bttb_status_string.restype = ctypes.c_char_p
+    L.bttb_last_error.argtypes = []
+    L.bttb_last_error.restype = ctypes.c_char_p
+    for name in ["bttb_plan_create", "bttb_plan_destroy", "bttb_plan_query", "bttb_kernel_generate",
+                 "bttb_forward", "bttb_transpose", "bttb_forward_profiled", "bttb_transpose_profiled",
+                 "bttb_debug_generator"]:
+        getattr(L, name).restype = ctypes.c_int
+    _handle = L
+    return L
+
+
+def check(fn: str, status: int):
+    if status != BTTB_OK:
+        msg = load().bttb_last_error().decode(errors="replace")
+        raise BttbError(fn, status, msg)

@@ -1,0 +1,514 @@
+// bttb_host.hip -- host side of libbttb.so: plan validation and sizes, the
+// launch sequences of kernel generation and of the two products, and the
+// extern "C" entry points declared in include/bttb.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/bttb.h"
+#include "bttb_internal.h"
+
+using namespace bttbk;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+bttb_status fail(bttb_status s, const std::string& msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int next_pow2(int64_t v)
+{
+    int64_t p = 1;
+    while (p < v) p <<= 1;
+    return (int)p;
+}
+
+}  // namespace
+
+struct bttb_plan_s {
+    bttb_problem_desc d;
+    std::vector<double> z;       // nz + 1 depth edges
+    int nx, ny, nz, sx, sy;
+    int Nx, Ny, ncols;           // transform lengths, ncols = Nx / 2 + 1
+    bool fp64;
+    int acc;                     // ACC_* for the FP32 forward depth sum
+    double scale;
+    MagWeights w;
+    size_t esz;                  // bytes of one real element (4 or 8)
+    // spectra blob layout
+    size_t off_tw64x, off_tw64y, off_twx, off_twy, off_spec, spec_bytes;
+    // generation batch
+    int gen_batch;
+};
+
+namespace {
+
+bttb_status validate_and_fill(const bttb_problem_desc* d, bttb_plan_s* P)
+{
+    if (d->problem != BTTB_GRAVITY_GZ && d->problem != BTTB_MAGNETIC_TMI && d->problem != BTTB_PROBE)
+        return fail(BTTB_ERR_INVALID_VALUE, "problem must be BTTB_GRAVITY_GZ, BTTB_MAGNETIC_TMI or BTTB_PROBE");
+    if (d->precision != BTTB_FP32 && d->precision != BTTB_FP64)
+        return fail(BTTB_ERR_INVALID_VALUE, "precision must be BTTB_FP32 or BTTB_FP64");
+    if (d->sx < 1 || d->sy < 1 || d->nz < 1)
+        return fail(BTTB_ERR_INVALID_VALUE, "sx, sy and nz must be >= 1");
+    if (d->pxl < 0 || d->pxr < 0 || d->pyl < 0 || d->pyr < 0)
+        return fail(BTTB_ERR_INVALID_VALUE, "paddings must be >= 0");
+    const int64_t nx = (int64_t)d->sx + d->pxl + d->pxr, ny = (int64_t)d->sy + d->pyl + d->pyr;
+    if ((d->nx != 0 && d->nx != nx) || (d->ny != 0 && d->ny != ny))
+        return fail(BTTB_ERR_INVALID_VALUE, "nx, ny must equal sx + pxl + pxr, sy + pyl + pyr (or be 0)");
+    if (nx > 1000000 || ny > 1000000 || d->nz > 1000000)
+        return fail(BTTB_ERR_UNSUPPORTED, "grid dimension too large");
+    auto finite_pos = [](double v) { return std::isfinite(v) && v > 0.0; };
+    if (!finite_pos(d->dx) || !finite_pos(d->dy))
+        return fail(BTTB_ERR_INVALID_VALUE, "dx and dy must be finite and > 0");
+    if (!std::isfinite(d->station_height) || d->station_height < 0.0)
+        return fail(BTTB_ERR_INVALID_VALUE, "station_height must be finite and >= 0");
+    P->z.assign((size_t)d->nz + 1, 0.0);
+    if (d->z_edges) {
+        for (int r = 0; r <= d->nz; ++r) P->z[r] = d->z_edges[r];
+        if (!std::isfinite(P->z[0]) || P->z[0] < 0.0)
+            return fail(BTTB_ERR_INVALID_VALUE, "z_edges[0] must be finite and >= 0");
+        for (int r = 0; r < d->nz; ++r)
+            if (!std::isfinite(P->z[r + 1]) || !(P->z[r + 1] > P->z[r]))
+                return fail(BTTB_ERR_INVALID_VALUE, "z_edges must be finite and strictly increasing");
+    } else {
+        if (!finite_pos(d->dz)) return fail(BTTB_ERR_INVALID_VALUE, "dz must be finite and > 0");
+        for (int r = 0; r <= d->nz; ++r) P->z[r] = r * d->dz;
+    }
+    if (!std::isfinite(d->scale)) return fail(BTTB_ERR_INVALID_VALUE, "scale must be finite");
+    if (d->problem == BTTB_MAGNETIC_TMI) {
+        if (!std::isfinite(d->inclination_deg) || d->inclination_deg < -90.0 || d->inclination_deg > 90.0)
+            return fail(BTTB_ERR_INVALID_VALUE, "inclination_deg must be in [-90, 90]");
+        if (!std::isfinite(d->declination_deg))
+            return fail(BTTB_ERR_INVALID_VALUE, "declination_deg must be finite");
+        if (!finite_pos(d->field_nT)) return fail(BTTB_ERR_INVALID_VALUE, "field_nT must be finite and > 0");
+    }
+    if (d->accumulation < BTTB_ACC_DEFAULT || d->accumulation > BTTB_ACC_WIDE)
+        return fail(BTTB_ERR_INVALID_VALUE, "accumulation must be a bttb_accumulation value");
+
+    const int64_t minx = std::max<int64_t>(8, d->sx + nx - 1), miny = std::max<int64_t>(8, d->sy + ny - 1);
+    int64_t Nx = d->nx_fft, Ny = d->ny_fft;
+    if (Nx < 0 || Ny < 0) return fail(BTTB_ERR_INVALID_VALUE, "nx_fft, ny_fft must be >= 0");
+    if (Nx == 0) Nx = next_pow2(minx);
+    if (Ny == 0) Ny = next_pow2(miny);
+    if (Nx < minx || Ny < miny)
+        return fail(BTTB_ERR_INVALID_VALUE, "nx_fft, ny_fft must be >= max(8, s + n - 1) (no circular aliasing)");
+    if (!is_pow2(Nx) || !is_pow2(Ny))
+        return fail(BTTB_ERR_UNSUPPORTED, "FFT lengths must be powers of two");
+    if (Nx > 4096 || Ny > 4096) return fail(BTTB_ERR_UNSUPPORTED, "FFT lengths above 4096 are not supported");
+
+    P->d = *d;
+    P->d.z_edges = nullptr;
+    P->nx = (int)nx;
+    P->ny = (int)ny;
+    P->nz = d->nz;
+    P->sx = d->sx;
+    P->sy = d->sy;
+    P->Nx = (int)Nx;
+    P->Ny = (int)Ny;
+    P->ncols = (int)Nx / 2 + 1;
+    P->fp64 = d->precision == BTTB_FP64;
+    P->esz = P->fp64 ? 8 : 4;
+    P->acc = d->accumulation == BTTB_ACC_PLAIN ? ACC_PLAIN
+           : d->accumulation == BTTB_ACC_TWOSUM ? ACC_TWOSUM : ACC_WIDE;
+    // magnetic weights for the field direction (L, M, N) = (cos I cos D,
+    // cos I sin D, sin I), x North, y East, z down; Laplace-eliminated form
+    // of f^T U f: 2MN U_yz + 2LN U_xz + 2LM U_xy + (N^2 - M^2)(-U_yy) + (N^2 - L^2)(-U_xx)
+    const double I = d->inclination_deg * M_PI / 180.0, D = d->declination_deg * M_PI / 180.0;
+    const double L = std::cos(I) * std::cos(D), M = std::cos(I) * std::sin(D), N = std::sin(I);
+    P->w.g[0] = 2 * M * N;
+    P->w.g[1] = 2 * L * N;
+    P->w.g[2] = 2 * L * M;
+    P->w.g[3] = N * N - M * M;
+    P->w.g[4] = N * N - L * L;
+    if (d->scale != 0.0) P->scale = d->scale;
+    else if (d->problem == BTTB_GRAVITY_GZ) P->scale = 6.6743e-11 * 1e3 * 1e5;  // mGal per (g/cm^3 m)
+    else if (d->problem == BTTB_MAGNETIC_TMI) P->scale = d->field_nT / (4.0 * M_PI);
+    else P->scale = 1.0;
+
+    // spectra blob: FP64 twiddles (x, y), working-precision twiddles, spectra
+    size_t off = 0;
+    P->off_tw64x = off; off = align_up(off + (size_t)Nx * 16);
+    P->off_tw64y = off; off = align_up(off + (size_t)Ny * 16);
+    if (P->fp64) {
+        P->off_twx = P->off_tw64x;
+        P->off_twy = P->off_tw64y;
+    } else {
+        P->off_twx = off; off = align_up(off + (size_t)Nx * 8);
+        P->off_twy = off; off = align_up(off + (size_t)Ny * 8);
+    }
+    P->off_spec = off;
+    const size_t csz = 2 * P->esz;
+    off = align_up(off + (size_t)P->nz * P->ncols * (size_t)Ny * csz);
+    P->spec_bytes = off;
+    P->gen_batch = std::min(P->nz, MAX_GEN_BATCH);
+    return BTTB_OK;
+}
+
+struct WsLayout {
+    size_t gen_a, gen_b, gen_total;
+    size_t fwd_x, fwd_y, fwd_total;
+    size_t tr_r, tr_z, tr_total;
+    size_t total;
+};
+
+WsLayout ws_layout(const bttb_plan_s* P, int nrhs)
+{
+    WsLayout L{};
+    const size_t csz = 2 * P->esz;
+    L.gen_a = 0;
+    L.gen_b = align_up((size_t)P->gen_batch * P->Nx * (size_t)P->Ny * 8);
+    L.gen_total = align_up(L.gen_b + (size_t)P->gen_batch * P->ncols * (size_t)P->Ny * 16);
+    L.fwd_x = 0;
+    L.fwd_y = align_up((size_t)nrhs * P->nz * P->ncols * (size_t)P->ny * csz);
+    L.fwd_total = align_up(L.fwd_y + (size_t)nrhs * P->ncols * (size_t)P->sy * csz);
+    L.tr_r = 0;
+    L.tr_z = align_up((size_t)nrhs * P->ncols * (size_t)P->sy * csz);
+    L.tr_total = align_up(L.tr_z + (size_t)nrhs * P->nz * P->ncols * (size_t)P->ny * csz);
+    L.total = std::max({L.gen_total, L.fwd_total, L.tr_total});
+    return L;
+}
+
+bttb_status hip_check(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return BTTB_OK;
+    return fail(BTTB_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+GenParams gen_params(const bttb_plan_s* P, int r0, int nl)
+{
+    GenParams g{};
+    g.kind = P->d.problem == BTTB_GRAVITY_GZ ? KIND_GRAVITY
+           : P->d.problem == BTTB_MAGNETIC_TMI ? KIND_MAGNETIC : KIND_PROBE;
+    g.sx = P->sx; g.sy = P->sy; g.nx = P->nx; g.ny = P->ny;
+    g.pxl = P->d.pxl; g.pyl = P->d.pyl;
+    g.Nx = P->Nx; g.Ny = P->Ny;
+    g.dx = P->d.dx; g.dy = P->d.dy; g.h = P->d.station_height; g.scale = P->scale;
+    for (int k = 0; k <= nl; ++k) g.z[k] = P->z[r0 + k];
+    g.w = P->w;
+    return g;
+}
+
+template <typename T>
+bttb_status run_generate(const bttb_plan_s* P, char* spec, char* ws, hipStream_t s)
+{
+    double2* tw64x = (double2*)(spec + P->off_tw64x);
+    double2* tw64y = (double2*)(spec + P->off_tw64y);
+    float2* tw32x = P->fp64 ? nullptr : (float2*)(spec + P->off_twx);
+    float2* tw32y = P->fp64 ? nullptr : (float2*)(spec + P->off_twy);
+    bttb_status st;
+    if ((st = hip_check(launch_twiddles(tw64x, tw32x, P->Nx, s), "twiddles x")) != BTTB_OK) return st;
+    if ((st = hip_check(launch_twiddles(tw64y, tw32y, P->Ny, s), "twiddles y")) != BTTB_OK) return st;
+    const WsLayout L = ws_layout(P, 1);
+    double* g64 = (double*)(ws + L.gen_a);
+    double2* w64 = (double2*)(ws + L.gen_b);
+    cT<T>* out = (cT<T>*)(spec + P->off_spec);
+    const double inv = 1.0 / ((double)P->Nx * (double)P->Ny);
+    for (int r0 = 0; r0 < P->nz; r0 += P->gen_batch) {
+        const int nl = std::min(P->gen_batch, P->nz - r0);
+        const GenParams g = gen_params(P, r0, nl);
+        if ((st = hip_check(launch_generate(g, r0, nl, g64, s), "generate")) != BTTB_OK) return st;
+        if ((st = hip_check(launch_rows_r2c<double, double>(P->Nx, g64, (int64_t)P->Nx * P->Ny, P->Nx, P->Nx,
+                                                            P->Ny, nl, w64, (int64_t)P->ncols * P->Ny, P->Ny,
+                                                            tw64x, s), "generator rows")) != BTTB_OK)
+            return st;
+        if ((st = hip_check(launch_cols_spec<T>(P->Ny, w64, P->ncols, nl, out, r0, inv, tw64y, s),
+                            "generator columns")) != BTTB_OK)
+            return st;
+    }
+    return BTTB_OK;
+}
+
+// ev: optional array of 4 events recorded before the first kernel and after
+// each of the three kernels (profiling entry points only)
+bttb_status record(hipEvent_t* ev, int k, hipStream_t s)
+{
+    if (!ev) return BTTB_OK;
+    return hip_check(hipEventRecord(ev[k], s), "event record");
+}
+
+template <typename T>
+bttb_status run_forward(const bttb_plan_s* P, const char* spec, const T* m, T* d, int nrhs, char* ws,
+                        hipStream_t s, hipEvent_t* ev = nullptr)
+{
+    const WsLayout L = ws_layout(P, nrhs);
+    cT<T>* X = (cT<T>*)(ws + L.fwd_x);
+    cT<T>* Y = (cT<T>*)(ws + L.fwd_y);
+    const cT<T>* twx = (const cT<T>*)(spec + P->off_twx);
+    const cT<T>* twy = (const cT<T>*)(spec + P->off_twy);
+    const cT<T>* sp = (const cT<T>*)(spec + P->off_spec);
+    bttb_status st;
+    if ((st = record(ev, 0, s)) != BTTB_OK) return st;
+    if ((st = hip_check(launch_rows_r2c<T, T>(P->Nx, m, (int64_t)P->nx * P->ny, P->nx, P->nx, P->ny,
+                                              nrhs * P->nz, X, (int64_t)P->ncols * P->ny, P->ny, twx, s),
+                        "forward rows")) != BTTB_OK)
+        return st;
+    if ((st = record(ev, 1, s)) != BTTB_OK) return st;
+    hipError_t e;
+    if constexpr (sizeof(T) == 8) {
+        e = launch_cols_fwd<T, ACC_PLAIN>(P->Ny, X, P->ny, P->ny, P->nz, P->ncols, sp, Y, P->sy, P->sy, nrhs,
+                                          twy, s);
+    } else {
+        if (P->acc == ACC_PLAIN)
+            e = launch_cols_fwd<T, ACC_PLAIN>(P->Ny, X, P->ny, P->ny, P->nz, P->ncols, sp, Y, P->sy, P->sy,
+                                              nrhs, twy, s);
+        else if (P->acc == ACC_TWOSUM)
+            e = launch_cols_fwd<T, ACC_TWOSUM>(P->Ny, X, P->ny, P->ny, P->nz, P->ncols, sp, Y, P->sy, P->sy,
+                                               nrhs, twy, s);
+        else
+            e = launch_cols_fwd<T, ACC_WIDE>(P->Ny, X, P->ny, P->ny, P->nz, P->ncols, sp, Y, P->sy, P->sy,
+                                             nrhs, twy, s);
+    }
+    if ((st = hip_check(e, "forward columns")) != BTTB_OK) return st;
+    if ((st = record(ev, 2, s)) != BTTB_OK) return st;
+    if ((st = hip_check(launch_rows_c2r<T>(P->Nx, Y, (int64_t)P->ncols * P->sy, P->sy, P->sy, nrhs, d,
+                                           (int64_t)P->sx * P->sy, P->sx, P->sx, twx, s),
+                        "forward output rows")) != BTTB_OK)
+        return st;
+    return record(ev, 3, s);
+}
+
+template <typename T>
+bttb_status run_transpose(const bttb_plan_s* P, const char* spec, const T* r, T* mt, int nrhs, char* ws,
+                          hipStream_t s, hipEvent_t* ev = nullptr)
+{
+    const WsLayout L = ws_layout(P, nrhs);
+    cT<T>* R = (cT<T>*)(ws + L.tr_r);
+    cT<T>* Z = (cT<T>*)(ws + L.tr_z);
+    const cT<T>* twx = (const cT<T>*)(spec + P->off_twx);
+    const cT<T>* twy = (const cT<T>*)(spec + P->off_twy);
+    const cT<T>* sp = (const cT<T>*)(spec + P->off_spec);
+    bttb_status st;
+    if ((st = record(ev, 0, s)) != BTTB_OK) return st;
+    if ((st = hip_check(launch_rows_r2c<T, T>(P->Nx, r, (int64_t)P->sx * P->sy, P->sx, P->sx, P->sy, nrhs, R,
+                                              (int64_t)P->ncols * P->sy, P->sy, twx, s),
+                        "transpose rows")) != BTTB_OK)
+        return st;
+    if ((st = record(ev, 1, s)) != BTTB_OK) return st;
+    if ((st = hip_check(launch_cols_tr<T>(P->Ny, R, P->sy, P->sy, P->nz, P->ncols, sp, Z, P->ny, P->ny, nrhs,
+                                          twy, s),
+                        "transpose columns")) != BTTB_OK)
+        return st;
+    if ((st = record(ev, 2, s)) != BTTB_OK) return st;
+    if ((st = hip_check(launch_rows_c2r<T>(P->Nx, Z, (int64_t)P->ncols * P->ny, P->ny, P->ny, nrhs * P->nz, mt,
+                                           (int64_t)P->nx * P->ny, P->nx, P->nx, twx, s),
+                        "transpose output rows")) != BTTB_OK)
+        return st;
+    return record(ev, 3, s);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// extern "C" entry points
+// ---------------------------------------------------------------------------
+extern "C" {
+
+bttb_status bttb_plan_create(const bttb_problem_desc* desc, bttb_plan_t* out)
+{
+    try {
+        g_last_error.clear();
+        if (!desc || !out) return fail(BTTB_ERR_NULL_POINTER, "desc and out must not be NULL");
+        *out = nullptr;
+        bttb_plan_s* P = new (std::nothrow) bttb_plan_s();
+        if (!P) return fail(BTTB_ERR_INTERNAL, "out of host memory");
+        bttb_status st = validate_and_fill(desc, P);
+        if (st != BTTB_OK) {
+            delete P;
+            return st;
+        }
+        *out = P;
+        return BTTB_OK;
+    } catch (...) {
+        return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_plan_create");
+    }
+}
+
+bttb_status bttb_plan_destroy(bttb_plan_t plan)
+{
+    delete plan;
+    return BTTB_OK;
+}
+
+bttb_status bttb_plan_query(bttb_plan_t plan, int32_t nrhs, size_t* spectra_bytes, size_t* workspace_bytes,
+                            int32_t* nx_fft, int32_t* ny_fft)
+{
+    g_last_error.clear();
+    if (!plan) return fail(BTTB_ERR_NULL_POINTER, "plan must not be NULL");
+    if (nrhs < 1) return fail(BTTB_ERR_INVALID_VALUE, "nrhs must be >= 1");
+    if (spectra_bytes) *spectra_bytes = plan->spec_bytes;
+    if (workspace_bytes) *workspace_bytes = ws_layout(plan, nrhs).total;
+    if (nx_fft) *nx_fft = plan->Nx;
+    if (ny_fft) *ny_fft = plan->Ny;
+    return BTTB_OK;
+}
+
+bttb_status bttb_kernel_generate(bttb_plan_t plan, void* spectra, void* workspace, size_t ws_bytes, void* stream)
+{
+    try {
+        g_last_error.clear();
+        if (!plan || !spectra || !workspace) return fail(BTTB_ERR_NULL_POINTER, "plan, spectra and workspace must not be NULL");
+        if (!aligned(spectra, kAlign) || !aligned(workspace, 16))
+            return fail(BTTB_ERR_INVALID_VALUE, "spectra must be 256-byte aligned and workspace 16-byte aligned");
+        if (ws_bytes < ws_layout(plan, 1).total)
+            return fail(BTTB_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than bttb_plan_query(plan, 1) reports");
+        hipStream_t s = (hipStream_t)stream;
+        return plan->fp64 ? run_generate<double>(plan, (char*)spectra, (char*)workspace, s)
+                          : run_generate<float>(plan, (char*)spectra, (char*)workspace, s);
+    } catch (...) {
+        return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_kernel_generate");
+    }
+}
+
+static bttb_status check_product_args(bttb_plan_t plan, const void* spectra, const void* in, void* out,
+                                      int32_t nrhs, void* workspace, size_t ws_bytes)
+{
+    if (!plan || !spectra || !in || !out || !workspace)
+        return fail(BTTB_ERR_NULL_POINTER, "plan, spectra, input, output and workspace must not be NULL");
+    if (nrhs < 1) return fail(BTTB_ERR_INVALID_VALUE, "nrhs must be >= 1");
+    if (!aligned(spectra, kAlign) || !aligned(workspace, 16) || !aligned(in, plan->esz) || !aligned(out, plan->esz))
+        return fail(BTTB_ERR_INVALID_VALUE, "misaligned buffer (spectra 256 B, workspace 16 B, vectors element size)");
+    if (ws_bytes < ws_layout(plan, nrhs).total)
+        return fail(BTTB_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than bttb_plan_query(plan, nrhs) reports");
+    return BTTB_OK;
+}
+
+bttb_status bttb_forward(bttb_plan_t plan, const void* spectra, const void* m, void* d, int32_t nrhs,
+                         void* workspace, size_t ws_bytes, void* stream)
+{
+    try {
+        g_last_error.clear();
+        bttb_status st = check_product_args(plan, spectra, m, d, nrhs, workspace, ws_bytes);
+        if (st != BTTB_OK) return st;
+        hipStream_t s = (hipStream_t)stream;
+        return plan->fp64 ? run_forward<double>(plan, (const char*)spectra, (const double*)m, (double*)d, nrhs,
+                                                (char*)workspace, s)
+                          : run_forward<float>(plan, (const char*)spectra, (const float*)m, (float*)d, nrhs,
+                                               (char*)workspace, s);
+    } catch (...) {
+        return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_forward");
+    }
+}
+
+bttb_status bttb_transpose(bttb_plan_t plan, const void* spectra, const void* r, void* mt, int32_t nrhs,
+                           void* workspace, size_t ws_bytes, void* stream)
+{
+    try {
+        g_last_error.clear();
+        bttb_status st = check_product_args(plan, spectra, r, mt, nrhs, workspace, ws_bytes);
+        if (st != BTTB_OK) return st;
+        hipStream_t s = (hipStream_t)stream;
+        return plan->fp64 ? run_transpose<double>(plan, (const char*)spectra, (const double*)r, (double*)mt, nrhs,
+                                                  (char*)workspace, s)
+                          : run_transpose<float>(plan, (const char*)spectra, (const float*)r, (float*)mt, nrhs,
+                                                 (char*)workspace, s);
+    } catch (...) {
+        return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_transpose");
+    }
+}
+
+static bttb_status profiled(bool fwd, bttb_plan_t plan, const void* spectra, const void* in, void* out,
+                            int32_t nrhs, void* workspace, size_t ws_bytes, void* stream, float* kernel_ms)
+{
+    bttb_status st = check_product_args(plan, spectra, in, out, nrhs, workspace, ws_bytes);
+    if (st != BTTB_OK) return st;
+    if (!kernel_ms) return fail(BTTB_ERR_NULL_POINTER, "kernel_ms must not be NULL");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int k = 0; k < 4 && st == BTTB_OK; ++k) st = hip_check(hipEventCreate(&ev[k]), "event create");
+    if (st == BTTB_OK) {
+        const char* sp = (const char*)spectra;
+        char* ws = (char*)workspace;
+        if (fwd)
+            st = plan->fp64 ? run_forward<double>(plan, sp, (const double*)in, (double*)out, nrhs, ws, s, ev)
+                            : run_forward<float>(plan, sp, (const float*)in, (float*)out, nrhs, ws, s, ev);
+        else
+            st = plan->fp64 ? run_transpose<double>(plan, sp, (const double*)in, (double*)out, nrhs, ws, s, ev)
+                            : run_transpose<float>(plan, sp, (const float*)in, (float*)out, nrhs, ws, s, ev);
+    }
+    if (st == BTTB_OK) st = hip_check(hipEventSynchronize(ev[3]), "event synchronize");
+    for (int k = 0; k < 3 && st == BTTB_OK; ++k)
+        st = hip_check(hipEventElapsedTime(&kernel_ms[k], ev[k], ev[k + 1]), "event elapsed");
+    for (int k = 0; k < 4; ++k)
+        if (ev[k]) (void)hipEventDestroy(ev[k]);
+    return st;
+}
+
+bttb_status bttb_forward_profiled(bttb_plan_t plan, const void* spectra, const void* m, void* d, int32_t nrhs,
+                                  void* workspace, size_t ws_bytes, void* stream, float* kernel_ms)
+{
+    try {
+        g_last_error.clear();
+        return profiled(true, plan, spectra, m, d, nrhs, workspace, ws_bytes, stream, kernel_ms);
+    } catch (...) {
+        return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_forward_profiled");
+    }
+}
+
+bttb_status bttb_transpose_profiled(bttb_plan_t plan, const void* spectra, const void* r, void* mt, int32_t nrhs,
+                                    void* workspace, size_t ws_bytes, void* stream, float* kernel_ms)
+{
+    try {
+        g_last_error.clear();
+        return profiled(false, plan, spectra, r, mt, nrhs, workspace, ws_bytes, stream, kernel_ms);
+    } catch (...) {
+        return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_transpose_profiled");
+    }
+}
+
+bttb_status bttb_debug_generator(bttb_plan_t plan, int32_t layer, double* host_out, void* workspace,
+                                 size_t ws_bytes, void* stream)
+{
+    try {
+        g_last_error.clear();
+        if (!plan || !host_out || !workspace) return fail(BTTB_ERR_NULL_POINTER, "plan, host_out and workspace must not be NULL");
+        if (layer < 0 || layer >= plan->nz) return fail(BTTB_ERR_INVALID_VALUE, "layer out of range");
+        const size_t need = (size_t)plan->Nx * plan->Ny * 8;
+        if (ws_bytes < need || ws_bytes < ws_layout(plan, 1).total)
+            return fail(BTTB_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than bttb_plan_query(plan, 1) reports");
+        if (!aligned(workspace, 16)) return fail(BTTB_ERR_INVALID_VALUE, "workspace must be 16-byte aligned");
+        hipStream_t s = (hipStream_t)stream;
+        const GenParams g = gen_params(plan, layer, 1);
+        bttb_status st = hip_check(launch_generate(g, layer, 1, (double*)workspace, s), "generate");
+        if (st != BTTB_OK) return st;
+        if ((st = hip_check(hipMemcpyAsync(host_out, workspace, need, hipMemcpyDeviceToHost, s), "copy")) != BTTB_OK)
+            return st;
+        return hip_check(hipStreamSynchronize(s), "synchronize");
+    } catch (...) {
+        return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_debug_generator");
+    }
+}
+
+const char* bttb_status_string(bttb_status s)
+{
+    switch (s) {
+    case BTTB_OK: return "BTTB_OK";
+    case BTTB_ERR_INVALID_VALUE: return "BTTB_ERR_INVALID_VALUE";
+    case BTTB_ERR_NULL_POINTER: return "BTTB_ERR_NULL_POINTER";
+    case BTTB_ERR_UNSUPPORTED: return "BTTB_ERR_UNSUPPORTED";
+    case BTTB_ERR_WORKSPACE_TOO_SMALL: return "BTTB_ERR_WORKSPACE_TOO_SMALL";
+    case BTTB_ERR_HIP: return "BTTB_ERR_HIP";
+    case BTTB_ERR_INTERNAL: return "BTTB_ERR_INTERNAL";
+    }
+    return "unknown bttb_status";
+}
+
+const char* bttb_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,208 @@
+"""Python binding of libbttb.so with the C ABI's names.
+
+Every function marshals torch tensors (device memory) and torch's current
+HIP stream into the C entry points of include/bttb.h; all computation runs in
+the library's HIP kernels.  There is no fallback path: if libbttb.so is
+missing or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+_KIND = {"gravity": _lib.BTTB_GRAVITY_GZ, "magnetic": _lib.BTTB_MAGNETIC_TMI, "probe": _lib.BTTB_PROBE}
+_PREC = {"fp32": _lib.BTTB_FP32, "fp64": _lib.BTTB_FP64}
+_ACC = {"default": _lib.BTTB_ACC_DEFAULT, "plain": _lib.BTTB_ACC_PLAIN, "twosum": _lib.BTTB_ACC_TWOSUM,
+        "wide": _lib.BTTB_ACC_WIDE}
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(int(t.data_ptr()))
+
+
+def make_desc(problem: dict, precision: str = "fp32", accumulation: str = "default"):
+    """Build the C descriptor from a problem dict (see workloads.problem)."""
+    z = problem.get("z_edges")
+    keep = None
+    zp = None
+    if z is not None:
+        keep = np.ascontiguousarray(z, dtype=np.float64)
+        zp = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d = _lib.ProblemDesc(
+        problem=_KIND[problem["kind"]], precision=_PREC[precision],
+        nx=0, ny=0, nz=problem["nz"], sx=problem["sx"], sy=problem["sy"],
+        pxl=problem.get("pxl", 0), pxr=problem.get("pxr", 0), pyl=problem.get("pyl", 0),
+        pyr=problem.get("pyr", 0), dx=problem["dx"], dy=problem["dy"], dz=problem.get("dz", 0.0),
+        z_edges=zp, station_height=problem.get("h", 0.0),
+        inclination_deg=problem.get("incl", 90.0), declination_deg=problem.get("decl", 0.0),
+        field_nT=problem.get("field_nT", 50000.0), scale=problem.get("scale", 0.0),
+        nx_fft=problem.get("nx_fft", 0), ny_fft=problem.get("ny_fft", 0),
+        accumulation=_ACC[accumulation])
+    return d, keep
+
+
+def bttb_plan_create(problem: dict, precision: str = "fp32", accumulation: str = "default") -> int:
+    L = _lib.load()
+    d, keep = make_desc(problem, precision, accumulation)
+    h = ctypes.c_void_p()
+    check("bttb_plan_create", L.bttb_plan_create(ctypes.byref(d), ctypes.byref(h)))
+    del keep
+    return h.value
+
+
+def bttb_plan_destroy(plan: int) -> None:
+    check("bttb_plan_destroy", _lib.load().bttb_plan_destroy(ctypes.c_void_p(plan)))
+
+
+def bttb_plan_query(plan: int, nrhs: int = 1):
+    """Returns (spectra_bytes, workspace_bytes, nx_fft, ny_fft)."""
+    sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    nx, ny = ctypes.c_int32(), ctypes.c_int32()
+    check("bttb_plan_query", _lib.load().bttb_plan_query(ctypes.c_void_p(plan), nrhs, ctypes.byref(sb),
+                                                          ctypes.byref(wb), ctypes.byref(nx),
+                                                          ctypes.byref(ny)))
+    return sb.value, wb.value, nx.value, ny.value
+
+
+def bttb_kernel_generate(plan: int, spectra: torch.Tensor, workspace: torch.Tensor, stream=None) -> None:
+    check("bttb_kernel_generate",
+          _lib.load().bttb_kernel_generate(ctypes.c_void_p(plan), _ptr(spectra), _ptr(workspace),
+                                           workspace.numel() * workspace.element_size(),
+                                           _stream_ptr(stream)))
+
+
+def bttb_forward(plan: int, spectra: torch.Tensor, m: torch.Tensor, d: torch.Tensor, nrhs: int,
+                 workspace: torch.Tensor, stream=None) -> None:
+    check("bttb_forward",
+          _lib.load().bttb_forward(ctypes.c_void_p(plan), _ptr(spectra), _ptr(m), _ptr(d), nrhs,
+                                   _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                   _stream_ptr(stream)))
+
+
+def bttb_transpose(plan: int, spectra: torch.Tensor, r: torch.Tensor, mt: torch.Tensor, nrhs: int,
+                   workspace: torch.Tensor, stream=None) -> None:
+    check("bttb_transpose",
+          _lib.load().bttb_transpose(ctypes.c_void_p(plan), _ptr(spectra), _ptr(r), _ptr(mt), nrhs,
+                                     _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                     _stream_ptr(stream)))
+
+
+def _profiled(fn: str, plan, spectra, x, y, nrhs, workspace, stream):
+    ms = (ctypes.c_float * 3)()
+    check(fn, getattr(_lib.load(), fn)(ctypes.c_void_p(plan), _ptr(spectra), _ptr(x), _ptr(y), nrhs,
+                                       _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                       _stream_ptr(stream), ms))
+    return [float(v) for v in ms]
+
+
+def bttb_forward_profiled(plan: int, spectra, m, d, nrhs: int, workspace, stream=None):
+    """bttb_forward with per-kernel HIP-event timing; returns the 3 kernel times [ms]."""
+    return _profiled("bttb_forward_profiled", plan, spectra, m, d, nrhs, workspace, stream)
+
+
+def bttb_transpose_profiled(plan: int, spectra, r, mt, nrhs: int, workspace, stream=None):
+    """bttb_transpose with per-kernel HIP-event timing; returns the 3 kernel times [ms]."""
+    return _profiled("bttb_transpose_profiled", plan, spectra, r, mt, nrhs, workspace, stream)
+
+
+def bttb_debug_generator(plan: int, layer: int, workspace: torch.Tensor, stream=None) -> np.ndarray:
+    _, _, nx, ny = bttb_plan_query(plan, 1)
+    out = np.empty((ny, nx), dtype=np.float64)
+    check("bttb_debug_generator",
+          _lib.load().bttb_debug_generator(ctypes.c_void_p(plan), layer,
+                                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                           _stream_ptr(stream)))
+    return out
+
+
+class Plan:
+    """A plan plus its spectra, on one device.
+
+    ``Plan(problem, precision)`` validates the problem (host only);
+    ``generate()`` allocates the spectra and fills them on the GPU;
+    ``forward(m)`` / ``transpose(r)`` run the products on torch's current stream.
+    """
+
+    def __init__(self, problem: dict, precision: str = "fp32", accumulation: str = "default",
+                 device="cuda"):
+        self.problem = dict(problem)
+        self.precision = precision
+        self.dtype = torch.float32 if precision == "fp32" else torch.float64
+        self.device = torch.device(device)
+        self.handle = bttb_plan_create(problem, precision, accumulation)
+        self.spectra_bytes, self._ws1, self.nx_fft, self.ny_fft = bttb_plan_query(self.handle, 1)
+        self.sx, self.sy, self.nz = problem["sx"], problem["sy"], problem["nz"]
+        self.nx = self.sx + problem.get("pxl", 0) + problem.get("pxr", 0)
+        self.ny = self.sy + problem.get("pyl", 0) + problem.get("pyr", 0)
+        self.spectra = None
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                bttb_plan_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    # -- memory -----------------------------------------------------------
+    def workspace_bytes(self, nrhs: int = 1) -> int:
+        return bttb_plan_query(self.handle, nrhs)[1]
+
+    def workspace(self, nrhs: int = 1) -> torch.Tensor:
+        need = self.workspace_bytes(nrhs)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    # -- operations ---------------------------------------------------------
+    def generate(self, stream=None) -> "Plan":
+        if self.spectra is None:
+            self.spectra = torch.empty(self.spectra_bytes, dtype=torch.uint8, device=self.device)
+        bttb_kernel_generate(self.handle, self.spectra, self.workspace(1), stream)
+        return self
+
+    def _check_vec(self, t: torch.Tensor, tail, name):
+        if t.device.type != "cuda" or t.dtype != self.dtype or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous %s CUDA tensor" % (name, self.dtype))
+        if tuple(t.shape[-len(tail):]) != tuple(tail):
+            raise ValueError("%s has shape %s, expected [..., %s]" % (name, tuple(t.shape), tail))
+        return int(math.prod(t.shape[:-len(tail)]))
+
+    def forward(self, m: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if self.spectra is None:
+            raise RuntimeError("call generate() first")
+        nrhs = self._check_vec(m, (self.nz, self.ny, self.nx), "m")
+        if out is None:
+            out = torch.empty(m.shape[:-3] + (self.sy, self.sx), dtype=self.dtype, device=m.device)
+        self._check_vec(out, (self.sy, self.sx), "out")
+        bttb_forward(self.handle, self.spectra, m, out, nrhs, self.workspace(nrhs), stream)
+        return out
+
+    def transpose(self, r: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if self.spectra is None:
+            raise RuntimeError("call generate() first")
+        nrhs = self._check_vec(r, (self.sy, self.sx), "r")
+        if out is None:
+            out = torch.empty(r.shape[:-2] + (self.nz, self.ny, self.nx), dtype=self.dtype, device=r.device)
+        self._check_vec(out, (self.nz, self.ny, self.nx), "out")
+        bttb_transpose(self.handle, self.spectra, r, out, nrhs, self.workspace(nrhs), stream)
+        return out
+
+    def debug_generator(self, layer: int) -> np.ndarray:
+        return bttb_debug_generator(self.handle, layer, self.workspace(1))

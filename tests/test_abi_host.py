@@ -1,0 +1,135 @@
+"""Host-side tests of the C ABI (no GPU needed): the library loads, exports
+every symbol include/bttb.h declares, validates descriptors and reports
+sizes.  No call here launches a kernel."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1912_06976_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1912_06976_amd import build
+        build.build()
+    return _lib.load()
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "bttb.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:bttb_status|const char\*)\s+(bttb_\w+)\(", txt, re.M)))
+
+
+def test_exports_every_declared_symbol(lib):
+    from paper_1912_06976_amd import _lib
+    names = header_functions()
+    assert set(names) == set(_lib.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if l.strip())
+    for n in names:
+        assert n in exported, n
+        assert hasattr(lib, n)
+
+
+def test_status_strings(lib):
+    for code, name in [(0, "BTTB_OK"), (1, "BTTB_ERR_INVALID_VALUE"), (4, "BTTB_ERR_WORKSPACE_TOO_SMALL")]:
+        assert lib.bttb_status_string(code).decode() == name
+
+
+def _create(prob, prec="fp32", **over):
+    from paper_1912_06976_amd.plan import make_desc
+    from paper_1912_06976_amd import _lib
+    d, keep = make_desc(prob, prec)
+    for k, v in over.items():
+        setattr(d, k, v)
+    h = ctypes.c_void_p()
+    st = _lib.load().bttb_plan_create(ctypes.byref(d), ctypes.byref(h))
+    return st, h, _lib.load().bttb_last_error().decode()
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("sx", 0, 1), ("sy", -3, 1), ("nz", 0, 1), ("pxl", -1, 1), ("dx", 0.0, 1), ("dy", float("nan"), 1),
+    ("dz", -1.0, 1), ("station_height", -1.0, 1), ("problem", 7, 1), ("precision", 3, 1),
+    ("nx", 17, 1), ("nx_fft", 16, 1), ("nx_fft", 96, 3), ("ny_fft", 8192, 3), ("accumulation", 9, 1),
+])
+def test_invalid_descriptors_rejected(lib, field, value, status):
+    st, h, msg = _create(W.small_gravity(), **{field: value})
+    assert st == status and h.value is None and msg
+
+
+def test_magnetic_field_checks(lib):
+    st, _, _ = _create(W.magnetic_48x56(), inclination_deg=91.0)
+    assert st == 1
+    st, _, _ = _create(W.magnetic_48x56(), field_nT=0.0)
+    assert st == 1
+    st, h, _ = _create(W.magnetic_48x56())
+    assert st == 0
+    lib.bttb_plan_destroy(h)
+
+
+def test_z_edges_validation(lib):
+    pr = dict(W.small_gravity(), z_edges=[0.0, 10.0, 5.0, 20.0, 30.0, 40.0, 50.0, 60.0, 70.0])
+    st, _, msg = _create(pr)
+    assert st == 1 and "increasing" in msg
+    pr = dict(W.small_gravity(), z_edges=[0.0, 10.0, 15.0, 20.0, 30.0, 40.0, 50.0, 60.0, 70.0])
+    st, h, _ = _create(pr)
+    assert st == 0
+    lib.bttb_plan_destroy(h)
+
+
+def test_null_pointers(lib):
+    from paper_1912_06976_amd import _lib
+    h = ctypes.c_void_p()
+    assert lib.bttb_plan_create(None, ctypes.byref(h)) == 2
+    assert lib.bttb_plan_query(None, 1, None, None, None, None) == 2
+    assert lib.bttb_forward(None, None, None, None, 1, None, 0, None) == 2
+    assert lib.bttb_transpose(None, None, None, None, 1, None, 0, None) == 2
+    assert lib.bttb_kernel_generate(None, None, None, 0, None) == 2
+    assert lib.bttb_plan_destroy(None) == 0
+
+
+def test_sizes_and_fft_choice(lib):
+    import paper_1912_06976_amd as B
+    h = B.bttb_plan_create(W.gravity_1024(), "fp32")
+    sb, wb, nx, ny = B.bttb_plan_query(h, 1)
+    assert (nx, ny) == (2048, 2048)       # smallest power of two >= 1000 + 1024 - 1
+    # spectra: 128 layers x 2048 x 1025 complex64, plus twiddle tables
+    assert 128 * 2048 * 1025 * 8 <= sb <= 128 * 2048 * 1025 * 8 + 4 * 2048 * 16 + 4096
+    sb4, wb4, _, _ = B.bttb_plan_query(h, 4)
+    assert sb4 == sb and wb4 > wb
+    with pytest.raises(B.BttbError):
+        B.bttb_plan_query(h, 0)
+    B.bttb_plan_destroy(h)
+    h = B.bttb_plan_create(W.small_gravity(), "fp64")
+    assert B.bttb_plan_query(h, 1)[2:] == (32, 32)
+    B.bttb_plan_destroy(h)
+    h = B.bttb_plan_create(dict(W.small_gravity(), nx_fft=64, ny_fft=128), "fp64")
+    assert B.bttb_plan_query(h, 1)[2:] == (64, 128)
+    B.bttb_plan_destroy(h)
+
+
+def test_workspace_too_small_is_rejected_before_launch(lib):
+    # fake (never dereferenced) device pointers: the size check fails first
+    import paper_1912_06976_amd as B
+    h = B.bttb_plan_create(W.small_gravity(), "fp64")
+    _, wb, _, _ = B.bttb_plan_query(h, 2)
+    p = ctypes.c_void_p(1 << 20)
+    assert lib.bttb_forward(ctypes.c_void_p(h), p, p, p, 2, p, wb - 1, None) == 4
+    assert lib.bttb_transpose(ctypes.c_void_p(h), p, p, p, 2, p, wb - 1, None) == 4
+    assert lib.bttb_forward(ctypes.c_void_p(h), p, p, p, 0, p, wb, None) == 1
+    assert lib.bttb_kernel_generate(ctypes.c_void_p(h), ctypes.c_void_p(3), p, wb, None) == 1  # misaligned
+    B.bttb_plan_destroy(h)
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_1912_06976_amd import _lib
+    monkeypatch.setattr(_lib, "_handle", None)
+    with pytest.raises(RuntimeError):
+        _lib.load(str(tmp_path / "missing.so"))
