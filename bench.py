@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-stations", type=int, default=6)
     ap.add_argument("--cpu-prisms", type=int, default=48)
+    ap.add_argument("--layer-chunk", type=int, default=0,
+                    help="layers per transpose pass (descriptor field layer_chunk; 0 = all)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes 3 times (calibrates the "
                          "HBM byte counters of a profiler against a kernel of known traffic)")
@@ -140,6 +142,7 @@ def main():
         return
 
     pr = W.gravity_1024()
+    pr["layer_chunk"] = args.layer_chunk
     nx, ny, nz = W.dims(pr)
     cells = nx * ny * nz
     log("inputs: ellipsoid model and N(0,1) data, seeds 301 / 302")

@@ -102,6 +102,10 @@ typedef struct {
     int32_t nx_fft, ny_fft;    /* 0: smallest power of two >= max(8, s + n - 1); else a
                                   power of two in [max(8, s + n - 1), 4096]            */
     int32_t accumulation;      /* bttb_accumulation                                    */
+    int32_t layer_chunk;       /* tuning: layers per pass of the transpose product (0: all
+                                  layers); smaller chunks keep the per-layer intermediate
+                                  in the device's last-level cache and shrink the
+                                  workspace.  Results do not depend on it.              */
 } bttb_problem_desc;
 
 typedef struct bttb_plan_s* bttb_plan_t;

@@ -5,7 +5,8 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbttb.so")
+#: the in-tree build; BTTB_LIB selects another build of the same sources
+LIB_PATH = os.environ.get("BTTB_LIB", os.path.join(_HERE, "libbttb.so"))
 
 BTTB_OK = 0
 STATUS_NAMES = {0: "BTTB_OK", 1: "BTTB_ERR_INVALID_VALUE", 2: "BTTB_ERR_NULL_POINTER",
@@ -33,7 +34,7 @@ class ProblemDesc(ctypes.Structure):
         ("inclination_deg", ctypes.c_double), ("declination_deg", ctypes.c_double),
         ("field_nT", ctypes.c_double), ("scale", ctypes.c_double),
         ("nx_fft", ctypes.c_int32), ("ny_fft", ctypes.c_int32),
-        ("accumulation", ctypes.c_int32),
+        ("accumulation", ctypes.c_int32), ("layer_chunk", ctypes.c_int32),
     ]
 
 

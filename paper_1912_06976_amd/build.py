@@ -16,15 +16,16 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
-LIB = os.path.join(HERE, "libbttb.so")
-BUILD = os.path.join(ROOT, "_build")
+LIB = os.environ.get("BTTB_LIB_OUT", os.path.join(HERE, "libbttb.so"))
+BUILD = os.environ.get("BTTB_BUILD_DIR", os.path.join(ROOT, "_build"))
 SOURCES = ["bttb_kernels.hip", "bttb_host.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("BTTB_ARCH", "gfx950")
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wno-unused-command-line-argument", "-I" + os.path.join(ROOT, "include")]
+         "-Wno-unused-command-line-argument", "-I" + os.path.join(ROOT, "include"),
+         *os.environ.get("BTTB_EXTRA_FLAGS", "").split()]
 
 
 def _compile(src: str) -> str:

@@ -43,7 +43,7 @@ struct bttb_plan_s {
     bttb_problem_desc d;
     std::vector<double> z;       // nz + 1 depth edges
     int nx, ny, nz, sx, sy;
-    int Nx, Ny, ncols;           // transform lengths, ncols = Nx / 2 + 1
+    int Nx, Ny, ncols;           // transform lengths, ncols = Nx / 2 (packed half spectra)
     bool fp64;
     int acc;                     // ACC_* for the FP32 forward depth sum
     double scale;
@@ -51,8 +51,9 @@ struct bttb_plan_s {
     size_t esz;                  // bytes of one real element (4 or 8)
     // spectra blob layout
     size_t off_tw64x, off_tw64y, off_twx, off_twy, off_spec, spec_bytes;
-    // generation batch
+    // generation batch; layers per transpose pass
     int gen_batch;
+    int tr_chunk;
 };
 
 namespace {
@@ -99,6 +100,7 @@ bttb_status validate_and_fill(const bttb_problem_desc* d, bttb_plan_s* P)
     }
     if (d->accumulation < BTTB_ACC_DEFAULT || d->accumulation > BTTB_ACC_WIDE)
         return fail(BTTB_ERR_INVALID_VALUE, "accumulation must be a bttb_accumulation value");
+    if (d->layer_chunk < 0) return fail(BTTB_ERR_INVALID_VALUE, "layer_chunk must be >= 0");
 
     const int64_t minx = std::max<int64_t>(8, d->sx + nx - 1), miny = std::max<int64_t>(8, d->sy + ny - 1);
     int64_t Nx = d->nx_fft, Ny = d->ny_fft;
@@ -120,7 +122,7 @@ bttb_status validate_and_fill(const bttb_problem_desc* d, bttb_plan_s* P)
     P->sy = d->sy;
     P->Nx = (int)Nx;
     P->Ny = (int)Ny;
-    P->ncols = (int)Nx / 2 + 1;
+    P->ncols = (int)Nx / 2;
     P->fp64 = d->precision == BTTB_FP64;
     P->esz = P->fp64 ? 8 : 4;
     P->acc = d->accumulation == BTTB_ACC_PLAIN ? ACC_PLAIN
@@ -156,6 +158,7 @@ bttb_status validate_and_fill(const bttb_problem_desc* d, bttb_plan_s* P)
     off = align_up(off + (size_t)P->nz * P->ncols * (size_t)Ny * csz);
     P->spec_bytes = off;
     P->gen_batch = std::min(P->nz, MAX_GEN_BATCH);
+    P->tr_chunk = d->layer_chunk > 0 ? std::min(d->layer_chunk, P->nz) : P->nz;
     return BTTB_OK;
 }
 
@@ -178,7 +181,7 @@ WsLayout ws_layout(const bttb_plan_s* P, int nrhs)
     L.fwd_total = align_up(L.fwd_y + (size_t)nrhs * P->ncols * (size_t)P->sy * csz);
     L.tr_r = 0;
     L.tr_z = align_up((size_t)nrhs * P->ncols * (size_t)P->sy * csz);
-    L.tr_total = align_up(L.tr_z + (size_t)nrhs * P->nz * P->ncols * (size_t)P->ny * csz);
+    L.tr_total = align_up(L.tr_z + (size_t)nrhs * P->tr_chunk * P->ncols * (size_t)P->ny * csz);
     L.total = std::max({L.gen_total, L.fwd_total, L.tr_total});
     return L;
 }
@@ -301,15 +304,26 @@ bttb_status run_transpose(const bttb_plan_s* P, const char* spec, const T* r, T*
                         "transpose rows")) != BTTB_OK)
         return st;
     if ((st = record(ev, 1, s)) != BTTB_OK) return st;
-    if ((st = hip_check(launch_cols_tr<T>(P->Ny, R, P->sy, P->sy, P->nz, P->ncols, sp, Z, P->ny, P->ny, nrhs,
-                                          twy, s),
-                        "transpose columns")) != BTTB_OK)
-        return st;
-    if ((st = record(ev, 2, s)) != BTTB_OK) return st;
-    if ((st = hip_check(launch_rows_c2r<T>(P->Nx, Z, (int64_t)P->ncols * P->ny, P->ny, P->ny, nrhs * P->nz, mt,
-                                           (int64_t)P->nx * P->ny, P->nx, P->nx, twx, s),
-                        "transpose output rows")) != BTTB_OK)
-        return st;
+    const int LC = P->tr_chunk;
+    for (int r0 = 0; r0 < P->nz; r0 += LC) {
+        const int nl = std::min(LC, P->nz - r0);
+        if ((st = hip_check(launch_cols_tr<T>(P->Ny, R, P->sy, P->sy, r0, nl, P->ncols, sp, Z, P->ny, P->ny, nrhs,
+                                              twy, s),
+                            "transpose columns")) != BTTB_OK)
+            return st;
+        if (LC == P->nz && (st = record(ev, 2, s)) != BTTB_OK) return st;
+        for (int q = 0; q < nrhs; ++q) {
+            if ((st = hip_check(launch_rows_c2r<T>(P->Nx, Z + (size_t)q * nl * P->ncols * P->ny,
+                                                   (int64_t)P->ncols * P->ny, P->ny, P->ny, nl,
+                                                   mt + ((size_t)q * P->nz + r0) * P->nx * P->ny,
+                                                   (int64_t)P->nx * P->ny, P->nx, P->nx, twx, s),
+                                "transpose output rows")) != BTTB_OK)
+                return st;
+        }
+    }
+    // chunked passes interleave the two kernels: their joint time is
+    // reported as the column kernel's, the row kernel's as 0
+    if (LC < P->nz && (st = record(ev, 2, s)) != BTTB_OK) return st;
     return record(ev, 3, s);
 }
 

@@ -45,7 +45,7 @@ hipError_t launch_cols_fwd(int N, const cT<T>* X, int64_t ldx, int ny, int nz, i
                            const cT<T>* spec, cT<T>* Y, int64_t ldy, int sy, int nrhs,
                            const cT<T>* tw, hipStream_t s);
 template <typename T>
-hipError_t launch_cols_tr(int N, const cT<T>* R, int64_t ldr, int sy, int nz, int ncols,
+hipError_t launch_cols_tr(int N, const cT<T>* R, int64_t ldr, int sy, int r0, int nl, int ncols,
                           const cT<T>* spec, cT<T>* Z, int64_t ldz, int ny, int nrhs,
                           const cT<T>* tw, hipStream_t s);
 

@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "fft_core.h"
 #include "bttb_internal.h"
 
@@ -121,134 +123,210 @@ __global__ void k_generate(GenParams P, int r0, double* __restrict__ out)
 }
 
 // ---------------------------------------------------------------------------
+// half-spectrum format
+// ---------------------------------------------------------------------------
+// The x transform of a real row of even length N has N/2 + 1 distinct bins;
+// bins 0 and N/2 are real.  Every half spectrum is stored "packed" as N/2
+// complex values: slot 0 holds (X[0], X[N/2]) as (real, imaginary) and slot
+// k in [1, N/2) holds X[k].  Along y, the packed slot-0 column is then the
+// sum A + i B of two real sequences, whose transforms are Hermitian; the
+// column kernels separate them with the mirror index -k when they need them
+// individually (block 0 only).  The number of columns is exactly N/2.
+
+// hardware block b -> logical block such that the blocks that the hardware
+// places on one XCD (b mod 8) get consecutive logical indices
+__device__ __forceinline__ int xcd_order(int b, int G)
+{
+    const int xcd = b & 7, k = b >> 3;
+    const int per = G >> 3, rem = G & 7;
+    return xcd < rem ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
+}
+
+// ---------------------------------------------------------------------------
 // row transforms
 // ---------------------------------------------------------------------------
+#ifndef BTTB_ROW_PAIRS
+#define BTTB_ROW_PAIRS 4
+#endif
 template <typename T, int N> struct RowCfg {
     static constexpr int TPL = N / 8;
-    static constexpr int PAIRS = sizeof(T) == 4 ? (N <= 2048 ? (256 / TPL > 4 ? 256 / TPL : 4) : 2)
-                                                : (N <= 1024 ? (256 / TPL > 4 ? 256 / TPL : 4)
+    static constexpr int P0 = BTTB_ROW_PAIRS;       // pairs of rows per block for long rows
+    static constexpr int PAIRS = sizeof(T) == 4 ? (N <= 2048 ? (256 / TPL > P0 ? 256 / TPL : P0) : 2)
+                                                : (N <= 1024 ? (256 / TPL > P0 ? 256 / TPL : P0)
                                                              : (N == 2048 ? 2 : 1));
     static constexpr int RT = 2 * PAIRS;            // rows per block
     static constexpr int THREADS = PAIRS * TPL;
-    static constexpr int HALF = N / 2 + 1;          // columns of a half spectrum
+    static constexpr int HALF = N / 2;              // packed half-spectrum columns
     static constexpr int SROW = RT + 1;             // padded staging row
     static constexpr int STAGE = HALF * SROW;
     static constexpr int XCH = PAIRS * lds_line_elems(N);
     static constexpr int LDS = STAGE > XCH ? STAGE : XCH;
+    static constexpr int TWO = LDS;                 // offset of the LDS twiddle table
 };
 
+// Row kernels are persistent: gridDim.x blocks (about the number that fit on
+// the device at once) walk over the row groups g = lb, lb + G, lb + 2G, ...
+// (lb = XCD-ordered block index, so neighbouring groups, which share 128-byte
+// lines of the column-major half spectra, run on one XCD at the same time).
+// The loads of the next group are issued before the current group is
+// transformed, so memory latency overlaps the FFT.
+
 // in:  batch b, row y, column x at in[b * in_bs + y * in_ld + x], x < nvx valid
-// out: out[b * out_bs + kx * out_ld + y] for kx <= N/2, y < nrows
+// out: packed half spectra out[b * out_bs + kx * out_ld + y], kx < N/2, y < nrows
 template <typename TI, typename T, int N>
 __global__ void __launch_bounds__((RowCfg<T, N>::THREADS))
 k_rows_r2c(const TI* __restrict__ in, int64_t in_bs, int64_t in_ld, int nvx, int nrows,
            cT<T>* __restrict__ out, int64_t out_bs, int64_t out_ld, const cT<T>* __restrict__ tw,
-           int blocks_per_batch)
+           int blocks_per_batch, int total)
 {
     using C = RowCfg<T, N>;
     constexpr int TPL = C::TPL;
-    __shared__ cT<T> lds[C::LDS];
-    const int b = blockIdx.x / blocks_per_batch;
-    const int row0 = (blockIdx.x % blocks_per_batch) * C::RT;
+    __shared__ cT<T> lds[C::LDS + TableTwiddles<T, N>::size()];
+    const int G = gridDim.x;
     const int pr = threadIdx.x / TPL, t = threadIdx.x % TPL;
-    const int ra = row0 + 2 * pr, rb = ra + 1;
-    const TI* src = in + (int64_t)b * in_bs;
-    cT<T> v[8];
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        const int x = t + m * TPL;
-        T a = 0, c = 0;
-        if (x < nvx) {
-            if (ra < nrows) a = (T)src[(int64_t)ra * in_ld + x];
-            if (rb < nrows) c = (T)src[(int64_t)rb * in_ld + x];
-        }
-        v[m] = mk<T>(a, c);
-    }
-    LineTwiddles<T, N> twl;
-    twl.load(tw, t);
+    TableTwiddles<T, N>::build(lds + C::TWO, tw, threadIdx.x, C::THREADS);
+    __syncthreads();
+    const TableTwiddles<T, N> twl{lds + C::TWO};
     cT<T>* xl = lds + pr * lds_line_elems(N);
-    if (nvx <= N / 2) fft_line<T, N, -1, true>(v, xl, twl, t);
-    else fft_line<T, N, -1, false>(v, xl, twl, t);
-    // split Z = FFT(a + i c) into A = FFT(a), C = FFT(c):
-    // A[k] = (Z[k] + conj Z[N-k]) / 2, C[k] = (Z[k] - conj Z[N-k]) / (2 i)
-    __syncthreads();
+    auto load = [&](int g, cT<T> (&v)[8]) {
+        const int b = g / blocks_per_batch;
+        const int ra = (g % blocks_per_batch) * C::RT + 2 * pr, rb = ra + 1;
+        const TI* src = in + (int64_t)b * in_bs;
 #pragma unroll
-    for (int m = 0; m < 8; ++m) xl[lpad(t + m * TPL)] = v[m];
-    __syncthreads();
-    cT<T> A[5], Cc[5];
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-        const int k = t + m * TPL;
-        if (m < 4 || t == 0) {
-            const cT<T> z = v[m];
-            const cT<T> zr = xl[lpad((N - k) & (N - 1))];
-            A[m] = mk<T>((T)0.5 * (z.x + zr.x), (T)0.5 * (z.y - zr.y));
-            Cc[m] = mk<T>((T)0.5 * (z.y + zr.y), (T)0.5 * (zr.x - z.x));
+        for (int m = 0; m < 8; ++m) {
+            const int x = t + m * TPL;
+            T a = 0, c = 0;
+            if (x < nvx) {
+                if (ra < nrows) a = (T)src[(int64_t)ra * in_ld + x];
+                if (rb < nrows) c = (T)src[(int64_t)rb * in_ld + x];
+            }
+            v[m] = mk<T>(a, c);
         }
-    }
-    __syncthreads();
+    };
+    int g = xcd_order(blockIdx.x, G);
+    cT<T> v[8];
+    if (g < total) load(g, v);
+    for (; g < total; g += G) {
+        cT<T> vn[8];
+        if (g + G < total) load(g + G, vn);
+        const int b = g / blocks_per_batch;
+        const int row0 = (g % blocks_per_batch) * C::RT;
+        if (nvx <= N / 2) fft_line<T, N, -1, true>(v, xl, twl, t);
+        else fft_line<T, N, -1, false>(v, xl, twl, t);
+        // split Z = FFT(a + i c) into A = FFT(a), C = FFT(c):
+        // A[k] = (Z[k] + conj Z[N-k]) / 2, C[k] = (Z[k] - conj Z[N-k]) / (2 i)
+        __syncthreads();
 #pragma unroll
-    for (int m = 0; m < 5; ++m) {
-        const int k = t + m * TPL;
-        if (m < 4 || t == 0) {
+        for (int m = 0; m < 8; ++m) xl[lpad(t + m * TPL)] = v[m];
+        __syncthreads();
+        cT<T> A[5], Cc[5];
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            const int k = t + m * TPL;
+            if (m < 4 || t == 0) {
+                const cT<T> z = v[m];
+                const cT<T> zr = xl[lpad((N - k) & (N - 1))];
+                A[m] = mk<T>((T)0.5 * (z.x + zr.x), (T)0.5 * (z.y - zr.y));
+                Cc[m] = mk<T>((T)0.5 * (z.y + zr.y), (T)0.5 * (zr.x - z.x));
+            }
+        }
+        if (t == 0) {   // pack the real bins 0 and N/2 into slot 0
+            A[0] = mk<T>(A[0].x, A[4].x);
+            Cc[0] = mk<T>(Cc[0].x, Cc[4].x);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int k = t + m * TPL;
             lds[k * C::SROW + 2 * pr] = A[m];
             lds[k * C::SROW + 2 * pr + 1] = Cc[m];
         }
-    }
-    __syncthreads();
-    cT<T>* dst = out + (int64_t)b * out_bs;
-    for (int e = threadIdx.x; e < C::HALF * C::RT; e += C::THREADS) {
-        const int kx = e / C::RT, rr = e % C::RT;
-        if (row0 + rr < nrows) dst[(int64_t)kx * out_ld + row0 + rr] = lds[kx * C::SROW + rr];
+        __syncthreads();
+        cT<T>* dst = out + (int64_t)b * out_bs;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int e = threadIdx.x + i * C::THREADS;   // HALF * RT = 8 * THREADS
+            const int kx = e / C::RT, rr = e % C::RT;
+            if (row0 + rr < nrows) dst[(int64_t)kx * out_ld + row0 + rr] = lds[kx * C::SROW + rr];
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = vn[m];
     }
 }
 
-// in:  in[b * in_bs + kx * in_ld + y], kx <= N/2, y < nrows (half spectra)
+// in:  packed half spectra in[b * in_bs + kx * in_ld + y], kx < N/2, y < nrows
 // out: out[b * out_bs + y * out_ld + x] for x < nvx_out (real, unnormalised
 //      inverse transform; the 1/(Nx Ny) factor lives in the spectra)
 template <typename T, int N>
 __global__ void __launch_bounds__((RowCfg<T, N>::THREADS))
 k_rows_c2r(const cT<T>* __restrict__ in, int64_t in_bs, int64_t in_ld, int nrows,
            T* __restrict__ out, int64_t out_bs, int64_t out_ld, int nvx_out,
-           const cT<T>* __restrict__ tw, int blocks_per_batch)
+           const cT<T>* __restrict__ tw, int blocks_per_batch, int total)
 {
     using C = RowCfg<T, N>;
     constexpr int TPL = C::TPL;
-    __shared__ cT<T> lds[C::LDS];
-    const int b = blockIdx.x / blocks_per_batch;
-    const int row0 = (blockIdx.x % blocks_per_batch) * C::RT;
+    __shared__ cT<T> lds[C::LDS + TableTwiddles<T, N>::size()];
+    const int G = gridDim.x;
     const int pr = threadIdx.x / TPL, t = threadIdx.x % TPL;
-    const cT<T>* src = in + (int64_t)b * in_bs;
-    for (int e = threadIdx.x; e < C::HALF * C::RT; e += C::THREADS) {
-        const int kx = e / C::RT, rr = e % C::RT;
-        lds[kx * C::SROW + rr] = (row0 + rr < nrows) ? src[(int64_t)kx * in_ld + row0 + rr] : mk<T>(0, 0);
-    }
+    TableTwiddles<T, N>::build(lds + C::TWO, tw, threadIdx.x, C::THREADS);
     __syncthreads();
-    // Z[k] = A[k] + i C[k] over the full length, using Hermitian symmetry
-    // above N/2; the imaginary parts at k = 0 and k = N/2 are dropped (real
-    // transform convention)
-    cT<T> v[8];
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        const int k = t + m * TPL;
-        const int kk = k <= N / 2 ? k : N - k;
-        cT<T> A = lds[kk * C::SROW + 2 * pr], Cc = lds[kk * C::SROW + 2 * pr + 1];
-        if (k > N / 2) { A.y = -A.y; Cc.y = -Cc.y; }
-        if (kk == 0 || kk == N / 2) { A.y = 0; Cc.y = 0; }
-        v[m] = mk<T>(A.x - Cc.y, A.y + Cc.x);
-    }
-    LineTwiddles<T, N> twl;
-    twl.load(tw, t);
+    const TableTwiddles<T, N> twl{lds + C::TWO};
     cT<T>* xl = lds + pr * lds_line_elems(N);
-    fft_line<T, N, +1, false>(v, xl, twl, t);   // begins with a barrier
-    const int ra = row0 + 2 * pr, rb = ra + 1;
-    T* dst = out + (int64_t)b * out_bs;
+    // tile of the packed half spectra of RT rows: HALF * RT = 8 * THREADS
+    // elements, element e = threadIdx.x + i THREADS at (kx, row) = (e / RT, e % RT)
+    auto load = [&](int g, cT<T> (&tl)[8]) {
+        const int b = g / blocks_per_batch;
+        const int row0 = (g % blocks_per_batch) * C::RT;
+        const cT<T>* src = in + (int64_t)b * in_bs;
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        const int x = t + m * TPL;
-        if (x < nvx_out) {
-            if (ra < nrows) dst[(int64_t)ra * out_ld + x] = v[m].x;
-            if (rb < nrows) dst[(int64_t)rb * out_ld + x] = v[m].y;
+        for (int i = 0; i < 8; ++i) {
+            const int e = threadIdx.x + i * C::THREADS;
+            const int kx = e / C::RT, rr = e % C::RT;
+            tl[i] = (row0 + rr < nrows) ? src[(int64_t)kx * in_ld + row0 + rr] : mk<T>(0, 0);
+        }
+    };
+    int g = xcd_order(blockIdx.x, G);
+    cT<T> tl[8];
+    if (g < total) load(g, tl);
+    for (; g < total; g += G) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int e = threadIdx.x + i * C::THREADS;
+            lds[(e / C::RT) * C::SROW + e % C::RT] = tl[i];
+        }
+        __syncthreads();
+        if (g + G < total) load(g + G, tl);
+        // Z[k] = A[k] + i C[k] over the full length: slot 0 unpacks the real
+        // bins 0 and N/2, Hermitian symmetry gives k > N/2
+        cT<T> v[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int k = t + m * TPL;
+            const int kk = k <= N / 2 ? k : N - k;
+            cT<T> A, Cc;
+            if (kk == 0 || kk == N / 2) {
+                const cT<T> pa = lds[2 * pr], pc = lds[2 * pr + 1];
+                A = mk<T>(kk == 0 ? pa.x : pa.y, 0);
+                Cc = mk<T>(kk == 0 ? pc.x : pc.y, 0);
+            } else {
+                A = lds[kk * C::SROW + 2 * pr];
+                Cc = lds[kk * C::SROW + 2 * pr + 1];
+                if (k > N / 2) { A.y = -A.y; Cc.y = -Cc.y; }
+            }
+            v[m] = mk<T>(A.x - Cc.y, A.y + Cc.x);
+        }
+        fft_line<T, N, +1, false>(v, xl, twl, t);   // begins with a barrier
+        const int b = g / blocks_per_batch;
+        const int ra = (g % blocks_per_batch) * C::RT + 2 * pr, rb = ra + 1;
+        T* dst = out + (int64_t)b * out_bs;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int x = t + m * TPL;
+            if (x < nvx_out) {
+                if (ra < nrows) dst[(int64_t)ra * out_ld + x] = v[m].x;
+                if (rb < nrows) dst[(int64_t)rb * out_ld + x] = v[m].y;
+            }
         }
     }
 }
@@ -256,6 +334,11 @@ k_rows_c2r(const cT<T>* __restrict__ in, int64_t in_bs, int64_t in_ld, int nrows
 // ---------------------------------------------------------------------------
 // column transforms
 // ---------------------------------------------------------------------------
+// minimum waves per SIMD requested for the column kernels (bounds the VGPRs
+// the compiler may use: 512 / waves)
+#ifndef BTTB_COL_WAVES
+#define BTTB_COL_WAVES 2
+#endif
 template <int N> struct ColCfg {
     static constexpr int TPL = N / 8;
     static constexpr int CPW = TPL >= 256 ? 1 : 256 / TPL;   // columns per block
@@ -263,7 +346,9 @@ template <int N> struct ColCfg {
 };
 
 // spectra from the FP64 generator: in[(l * ncols + kx) * N + y] (l = layer in
-// batch) -> spec[((r0 + l) * ncols + kx) * N + ky] = FFT_y(in) * scale
+// batch, packed half spectra along x) -> spec[((r0 + l) * ncols + kx) * N + ky]
+// = FFT_y(in) * scale (column 0 becomes T^[0] + i T^[N/2], the packed pair of
+// Hermitian columns)
 template <typename T, int N>
 __global__ void __launch_bounds__(ColCfg<N>::THREADS)
 k_cols_spec(const double2* __restrict__ in, int ncols, cT<T>* __restrict__ spec, int r0, double scale,
@@ -277,7 +362,7 @@ k_cols_spec(const double2* __restrict__ in, int ncols, cT<T>* __restrict__ spec,
     const int l = blockIdx.y;
     const bool ok = col < ncols;
     double2 v[8];
-    const double2* src = in + ((int64_t)l * ncols + col) * N;
+    const double2* src = in + ((int64_t)l * ncols + (ok ? col : 0)) * N;
 #pragma unroll
     for (int m = 0; m < 8; ++m) v[m] = ok ? src[t + m * TPL] : make_double2(0.0, 0.0);
     LineTwiddles<double, N> twl;
@@ -319,22 +404,59 @@ template <typename T> struct Acc<T, ACC_WIDE> {
     __device__ __forceinline__ cT<T> get() const { return mk<T>((T)sx, (T)sy); }
 };
 
-// forward: X[((q * nz + r) * ncols + kx) * ldx + y], y < ny (row-pass output);
-// Y[(q * ncols + kx) * ldy + y], y < sy
+// Column 0 of the packed format holds z = A + i B with A, B the transforms
+// of two real sequences (Hermitian).  With zr = z at -k:
+//   A = (z + conj zr) / 2,  B = (z - conj zr) / (2 i).
+template <typename T> __device__ __forceinline__ cT<T> herm_a(cT<T> z, cT<T> zr) {
+    return mk<T>((T)0.5 * (z.x + zr.x), (T)0.5 * (z.y - zr.y));
+}
+template <typename T> __device__ __forceinline__ cT<T> herm_b(cT<T> z, cT<T> zr) {
+    return mk<T>((T)0.5 * (z.y + zr.y), (T)0.5 * (zr.x - z.x));
+}
+
+// Store two register lines (positions t + m TPL) into two LDS line buffers so
+// that their values at the mirror positions -k can be read back one at a
+// time.  Contains barriers: every thread of the block calls it; only
+// `active` threads write.
+template <typename T, int N>
+__device__ __forceinline__ void stage_pair(const cT<T> (&u)[8], const cT<T> (&w)[8], cT<T>* bu, cT<T>* bw,
+                                           int t, bool active)
+{
+    constexpr int TPL = N / 8;
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            bu[lpad(t + m * TPL)] = u[m];
+            bw[lpad(t + m * TPL)] = w[m];
+        }
+    }
+    __syncthreads();
+}
+template <int N> __device__ __forceinline__ int mirror_idx(int t, int m) {
+    return lpad((N - t - m * (N / 8)) & (N - 1));
+}
+
+// forward: X[((q * nz + r) * ncols + kx) * ldx + y], y < ny (packed row-pass
+// output); Y[(q * ncols + kx) * ldy + y], y < sy
 template <typename T, int N, int NR, int ACC>
-__global__ void __launch_bounds__(ColCfg<N>::THREADS)
+__global__ void __launch_bounds__(ColCfg<N>::THREADS, BTTB_COL_WAVES)
 k_cols_fwd_mac(const cT<T>* __restrict__ X, int64_t ldx, int ny, int nz, int ncols,
                const cT<T>* __restrict__ spec, cT<T>* __restrict__ Y, int64_t ldy, int sy,
                int nrhs, const cT<T>* __restrict__ tw)
 {
     using C = ColCfg<N>;
     constexpr int TPL = C::TPL;
-    __shared__ cT<T> lds[C::CPW * lds_line_elems(N)];
+    constexpr int LL = lds_line_elems(N);
+    __shared__ cT<T> lds[(C::CPW + 1) * LL];
     const int cl = threadIdx.x / TPL, t = threadIdx.x % TPL;
     const int col = blockIdx.x * C::CPW + cl;
     const int q0 = blockIdx.y * NR;
     const bool ok = col < ncols;
-    cT<T>* xl = lds + cl * lds_line_elems(N);
+    const bool packed_blk = blockIdx.x == 0;      // block holding column 0
+    const bool packed = packed_blk && cl == 0;
+    cT<T>* xl = lds + cl * LL;
+    cT<T>* xs2 = lds + C::CPW * LL;               // second buffer (column 0)
     LineTwiddles<T, N> twl;
     twl.load(tw, t);
     Acc<T, ACC> acc[NR][8];
@@ -343,69 +465,107 @@ k_cols_fwd_mac(const cT<T>* __restrict__ X, int64_t ldx, int ny, int nz, int nco
 #pragma unroll
         for (int m = 0; m < 8; ++m) acc[q][m].zero();
     const bool zhi = ny <= N / 2;
-    for (int r = 0; r < nz; ++r) {
-        cT<T> tv[8];
-        const cT<T>* sp = spec + ((int64_t)r * ncols + (ok ? col : 0)) * N;
+    const int ccol = ok ? col : 0;
+    // software pipeline: the next layer's spectra and input columns are
+    // loaded while the current layer is transformed
+    cT<T> tn[8], xn[NR][8];
+    auto load_layer = [&](int r) {
+        const cT<T>* sp = spec + ((int64_t)r * ncols + ccol) * N;
 #pragma unroll
-        for (int m = 0; m < 8; ++m) tv[m] = ok ? sp[t + m * TPL] : mk<T>(0, 0);
+        for (int m = 0; m < 8; ++m) tn[m] = sp[t + m * TPL];
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
             const int qq = q0 + q;
-            cT<T> v[8];
-            const cT<T>* xs = X + (((int64_t)(qq < nrhs ? qq : 0) * nz + r) * ncols + (ok ? col : 0)) * ldx;
+            const cT<T>* xs = X + (((int64_t)(qq < nrhs ? qq : 0) * nz + r) * ncols + ccol) * ldx;
 #pragma unroll
             for (int m = 0; m < 8; ++m) {
                 const int y = t + m * TPL;
-                v[m] = (ok && qq < nrhs && y < ny) ? xs[y] : mk<T>(0, 0);
+                xn[q][m] = (ok && qq < nrhs && y < ny) ? xs[y] : mk<T>(0, 0);
             }
-            if (zhi) fft_line<T, N, -1, true>(v, xl, twl, t);
-            else fft_line<T, N, -1, false>(v, xl, twl, t);
+        }
+    };
+    load_layer(0);
+    for (int r = 0; r < nz; ++r) {
+        cT<T> tv[8], v[NR][8];
 #pragma unroll
-            for (int m = 0; m < 8; ++m) acc[q][m].add(cmul<T>(tv[m], v[m]));
+        for (int m = 0; m < 8; ++m) tv[m] = tn[m];
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+#pragma unroll
+            for (int m = 0; m < 8; ++m) v[q][m] = xn[q][m];
+        if (r + 1 < nz) load_layer(r + 1);
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            if (zhi) fft_line<T, N, -1, true>(v[q], xl, twl, t);
+            else fft_line<T, N, -1, false>(v[q], xl, twl, t);
+            if (packed_blk) {
+                stage_pair<T, N>(v[q], tv, xl, xs2, t, packed);
+                if (packed) {
+                    // column 0 carries bins 0 and N/2: accumulate
+                    // T0 F0 + i T1 F1 of the separated Hermitian parts
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) {
+                        const int mi = mirror_idx<N>(t, m);
+                        const cT<T> vr = xl[mi], tr = xs2[mi];
+                        const cT<T> p0 = cmul<T>(herm_a<T>(tv[m], tr), herm_a<T>(v[q][m], vr));
+                        const cT<T> p1 = cmul<T>(herm_b<T>(tv[m], tr), herm_b<T>(v[q][m], vr));
+                        acc[q][m].add(mk<T>(p0.x - p1.y, p0.y + p1.x));
+                    }
+                    continue;
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < 8; ++m) acc[q][m].add(cmul<T>(tv[m], v[q][m]));
         }
     }
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
         const int qq = q0 + q;
-        cT<T> v[8];
+        cT<T> w[8];
 #pragma unroll
-        for (int m = 0; m < 8; ++m) v[m] = acc[q][m].get();
-        fft_line<T, N, +1, false>(v, xl, twl, t);
+        for (int m = 0; m < 8; ++m) w[m] = acc[q][m].get();
+        fft_line<T, N, +1, false>(w, xl, twl, t);
         if (ok && qq < nrhs) {
             cT<T>* ys = Y + ((int64_t)qq * ncols + col) * ldy;
 #pragma unroll
             for (int m = 0; m < 8; ++m) {
                 const int y = t + m * TPL;
-                if (y < sy) ys[y] = v[m];
+                if (y < sy) ys[y] = w[m];
             }
         }
     }
 }
 
-// transpose: R[(q * ncols + kx) * ldr + y], y < sy (row-pass output of the
-// data); Z[((q * nz + r) * ncols + kx) * ldz + y], y < ny
+// transpose over layers [r0, r0 + nl): R[(q * ncols + kx) * ldr + y], y < sy
+// (packed row-pass output of the data); Z[((q * nl + r - r0) * ncols + kx) * ldz + y],
+// y < ny
 template <typename T, int N, int NR>
-__global__ void __launch_bounds__(ColCfg<N>::THREADS)
-k_cols_tr_mac(const cT<T>* __restrict__ R, int64_t ldr, int sy, int nz, int ncols,
+__global__ void __launch_bounds__(ColCfg<N>::THREADS, BTTB_COL_WAVES)
+k_cols_tr_mac(const cT<T>* __restrict__ R, int64_t ldr, int sy, int r0, int nl, int ncols,
               const cT<T>* __restrict__ spec, cT<T>* __restrict__ Z, int64_t ldz, int ny,
               int nrhs, const cT<T>* __restrict__ tw)
 {
     using C = ColCfg<N>;
     constexpr int TPL = C::TPL;
-    __shared__ cT<T> lds[C::CPW * lds_line_elems(N)];
+    constexpr int LL = lds_line_elems(N);
+    __shared__ cT<T> lds[(C::CPW + 1) * LL];
     const int cl = threadIdx.x / TPL, t = threadIdx.x % TPL;
     const int col = blockIdx.x * C::CPW + cl;
     const int q0 = blockIdx.y * NR;
     const bool ok = col < ncols;
-    cT<T>* xl = lds + cl * lds_line_elems(N);
+    const bool packed_blk = blockIdx.x == 0;
+    const bool packed = packed_blk && cl == 0;
+    cT<T>* xl = lds + cl * LL;
+    cT<T>* xs2 = lds + C::CPW * LL;
     LineTwiddles<T, N> twl;
     twl.load(tw, t);
+    const int ccol = ok ? col : 0;
     cT<T> rh[NR][8];
     const bool zhi = sy <= N / 2;
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
         const int qq = q0 + q;
-        const cT<T>* rs = R + ((int64_t)(qq < nrhs ? qq : 0) * ncols + (ok ? col : 0)) * ldr;
+        const cT<T>* rs = R + ((int64_t)(qq < nrhs ? qq : 0) * ncols + ccol) * ldr;
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
             const int y = t + m * TPL;
@@ -414,20 +574,44 @@ k_cols_tr_mac(const cT<T>* __restrict__ R, int64_t ldr, int sy, int nz, int ncol
         if (zhi) fft_line<T, N, -1, true>(rh[q], xl, twl, t);
         else fft_line<T, N, -1, false>(rh[q], xl, twl, t);
     }
-    for (int r = 0; r < nz; ++r) {
-        cT<T> tv[8];
-        const cT<T>* sp = spec + ((int64_t)r * ncols + (ok ? col : 0)) * N;
+    cT<T> tn[8];
+    {
+        const cT<T>* sp = spec + ((int64_t)r0 * ncols + ccol) * N;
 #pragma unroll
-        for (int m = 0; m < 8; ++m) tv[m] = ok ? sp[t + m * TPL] : mk<T>(0, 0);
+        for (int m = 0; m < 8; ++m) tn[m] = sp[t + m * TPL];
+    }
+    for (int r = r0; r < r0 + nl; ++r) {
+        cT<T> tv[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) tv[m] = tn[m];
+        if (r + 1 < r0 + nl) {
+            const cT<T>* sp = spec + ((int64_t)(r + 1) * ncols + ccol) * N;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) tn[m] = sp[t + m * TPL];
+        }
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
             const int qq = q0 + q;
             cT<T> v[8];
 #pragma unroll
             for (int m = 0; m < 8; ++m) v[m] = cmulc<T>(rh[q][m], tv[m]);
+            if (packed_blk) {
+                stage_pair<T, N>(rh[q], tv, xl, xs2, t, packed);
+                if (packed) {
+                    // column 0: conj(T0) R0 + i conj(T1) R1
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) {
+                        const int mi = mirror_idx<N>(t, m);
+                        const cT<T> rr = xl[mi], tr = xs2[mi];
+                        const cT<T> p0 = cmulc<T>(herm_a<T>(rh[q][m], rr), herm_a<T>(tv[m], tr));
+                        const cT<T> p1 = cmulc<T>(herm_b<T>(rh[q][m], rr), herm_b<T>(tv[m], tr));
+                        v[m] = mk<T>(p0.x - p1.y, p0.y + p1.x);
+                    }
+                }
+            }
             fft_line<T, N, +1, false>(v, xl, twl, t);
             if (ok && qq < nrhs) {
-                cT<T>* zs = Z + (((int64_t)qq * nz + r) * ncols + col) * ldz;
+                cT<T>* zs = Z + (((int64_t)qq * nl + (r - r0)) * ncols + col) * ldz;
 #pragma unroll
                 for (int m = 0; m < 8; ++m) {
                     const int y = t + m * TPL;
@@ -455,6 +639,17 @@ k_cols_tr_mac(const cT<T>* __restrict__ R, int64_t ldr, int sy, int nz, int ncol
     case 4096: MACRO(4096); break;\
     default: return hipErrorInvalidValue; }
 
+// blocks of `kernel` that are resident on the whole current device at once
+// (occupancy per CU times the number of CUs); at least 1
+static int resident_blocks(const void* kernel, int threads)
+{
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || per < 1) per = 1;
+    return std::max(1, ncu * per);
+}
+
 hipError_t launch_twiddles(double2* t64, float2* t32, int n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_twiddles, dim3((n + 255) / 256), dim3(256), 0, s, t64, t32, n);
@@ -478,8 +673,12 @@ hipError_t launch_rows_r2c(int N, const TI* in, int64_t in_bs, int64_t in_ld, in
     {                                                                                      \
         using C = RowCfg<T, NN>;                                                           \
         const int bpb = (nrows + C::RT - 1) / C::RT;                                       \
-        hipLaunchKernelGGL((k_rows_r2c<TI, T, NN>), dim3(bpb * nbatch), dim3(C::THREADS), 0, s, \
-                           in, in_bs, in_ld, nvx, nrows, out, out_bs, out_ld, tw, bpb);    \
+        const int total = bpb * nbatch;                                                    \
+        static int resident = 0;                                                           \
+        if (!resident) resident = resident_blocks((const void*)k_rows_r2c<TI, T, NN>, C::THREADS); \
+        const int grid = std::min(total, resident);                                        \
+        hipLaunchKernelGGL((k_rows_r2c<TI, T, NN>), dim3(grid), dim3(C::THREADS), 0, s,    \
+                           in, in_bs, in_ld, nvx, nrows, out, out_bs, out_ld, tw, bpb, total); \
     }
     BTTB_LEN_SWITCH(N, L_R2C)
 #undef L_R2C
@@ -495,8 +694,12 @@ hipError_t launch_rows_c2r(int N, const cT<T>* in, int64_t in_bs, int64_t in_ld,
     {                                                                                      \
         using C = RowCfg<T, NN>;                                                           \
         const int bpb = (nrows + C::RT - 1) / C::RT;                                       \
-        hipLaunchKernelGGL((k_rows_c2r<T, NN>), dim3(bpb * nbatch), dim3(C::THREADS), 0, s, \
-                           in, in_bs, in_ld, nrows, out, out_bs, out_ld, nvx_out, tw, bpb); \
+        const int total = bpb * nbatch;                                                    \
+        static int resident = 0;                                                           \
+        if (!resident) resident = resident_blocks((const void*)k_rows_c2r<T, NN>, C::THREADS); \
+        const int grid = std::min(total, resident);                                        \
+        hipLaunchKernelGGL((k_rows_c2r<T, NN>), dim3(grid), dim3(C::THREADS), 0, s,        \
+                           in, in_bs, in_ld, nrows, out, out_bs, out_ld, nvx_out, tw, bpb, total); \
     }
     BTTB_LEN_SWITCH(N, L_C2R)
 #undef L_C2R
@@ -538,7 +741,7 @@ hipError_t launch_cols_fwd(int N, const cT<T>* X, int64_t ldx, int ny, int nz, i
 }
 
 template <typename T>
-hipError_t launch_cols_tr(int N, const cT<T>* R, int64_t ldr, int sy, int nz, int ncols,
+hipError_t launch_cols_tr(int N, const cT<T>* R, int64_t ldr, int sy, int r0, int nl, int ncols,
                           const cT<T>* spec, cT<T>* Z, int64_t ldz, int ny, int nrhs,
                           const cT<T>* tw, hipStream_t s)
 {
@@ -548,7 +751,7 @@ hipError_t launch_cols_tr(int N, const cT<T>* R, int64_t ldr, int sy, int nz, in
         using C = ColCfg<NN>;                                                              \
         dim3 grid((ncols + C::CPW - 1) / C::CPW, (nrhs + NR - 1) / NR);                    \
         hipLaunchKernelGGL((k_cols_tr_mac<T, NN, 1>), grid, dim3(C::THREADS), 0, s, R, ldr, sy, \
-                           nz, ncols, spec, Z, ldz, ny, nrhs, tw);                         \
+                           r0, nl, ncols, spec, Z, ldz, ny, nrhs, tw);                     \
     }
     BTTB_LEN_SWITCH(N, L_TR)
 #undef L_TR
@@ -580,9 +783,9 @@ template hipError_t launch_cols_fwd<float, ACC_TWOSUM>(int, const float2*, int64
 template hipError_t launch_cols_fwd<float, ACC_WIDE>(int, const float2*, int64_t, int, int, int,
                                                      const float2*, float2*, int64_t, int, int,
                                                      const float2*, hipStream_t);
-template hipError_t launch_cols_tr<double>(int, const double2*, int64_t, int, int, int, const double2*,
+template hipError_t launch_cols_tr<double>(int, const double2*, int64_t, int, int, int, int, const double2*,
                                            double2*, int64_t, int, int, const double2*, hipStream_t);
-template hipError_t launch_cols_tr<float>(int, const float2*, int64_t, int, int, int, const float2*,
+template hipError_t launch_cols_tr<float>(int, const float2*, int64_t, int, int, int, int, const float2*,
                                           float2*, int64_t, int, int, const float2*, hipStream_t);
 
 }  // namespace bttbk

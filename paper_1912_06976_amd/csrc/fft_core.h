@@ -41,10 +41,13 @@ template <typename T, int DIR> __device__ __forceinline__ cT<T> mul_i(cT<T> a) {
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n >> 1); }
 
-// padded LDS index: one pad element after every 8 spreads the strided
-// Stockham writes over the banks
-__device__ __forceinline__ int lpad(int x) { return x + (x >> 3); }
-constexpr int lds_line_elems(int n) { return n + (n >> 3); }
+// padded LDS index: one pad element after every 2^BTTB_LPAD_SHIFT spreads the
+// strided Stockham writes over the banks
+#ifndef BTTB_LPAD_SHIFT
+#define BTTB_LPAD_SHIFT 5
+#endif
+__device__ __forceinline__ int lpad(int x) { return x + (x >> BTTB_LPAD_SHIFT); }
+constexpr int lds_line_elems(int n) { return n + (n >> BTTB_LPAD_SHIFT); }
 
 template <int N> struct FftShape {
     static constexpr int LOG = ilog2(N);
@@ -121,6 +124,50 @@ template <typename T, int N> struct LineTwiddles {
     }
 };
 
+// Alternative twiddle source: a stage-major table (typically in LDS) that
+// saves the registers of LineTwiddles.  For radix-8 stage s >= 1 (L = 8^s)
+// it holds w^(i j N/(8L)) at [off_s + (i-1) L + j], j < L; for the final
+// radix-RL stage (L = N/RL) w^(i j) at [off_f + (i-1) L + j].  A stage's
+// reads by consecutive threads are consecutive (or broadcast) entries, so
+// they do not conflict on the LDS banks.
+template <typename T, int N> struct TableTwiddles {
+    const cT<T>* p;
+    // entries before stage s (1 <= s <= S8; s = S8 is the final small stage)
+    static constexpr int off(int s) {
+        int o = 0, L = 8;
+        for (int k = 1; k < s; ++k) { o += 7 * L; L *= 8; }
+        return o;
+    }
+    static constexpr int size() {
+        using S = FftShape<N>;
+        return off(S::S8) + (S::RL > 1 ? (S::RL - 1) * (N / S::RL) : 0);
+    }
+    // fill dst[0 .. size()) from the natural table tw (all threads of the block)
+    static __device__ void build(cT<T>* dst, const cT<T>* __restrict__ tw, int tid, int nthreads) {
+        using S = FftShape<N>;
+        for (int e = tid; e < size(); e += nthreads) {
+            int idx;
+            if (e < off(S::S8)) {
+                int s = 1, L = 8;
+                while (e >= off(s + 1)) { ++s; L *= 8; }
+                const int r = e - off(s), i = r / L + 1, j = r % L;
+                idx = i * j * (N / (8 * L));
+            } else {
+                const int L = N / S::RL, r = e - off(S::S8), i = r / L + 1, j = r % L;
+                idx = i * j;
+            }
+            dst[e] = tw[idx & (N - 1)];
+        }
+    }
+};
+
+template <typename T, int N>
+__device__ __forceinline__ cT<T> tw_get(const LineTwiddles<T, N>& tw, int c, int, int, int, int) { return tw.w[c]; }
+template <typename T, int N>
+__device__ __forceinline__ cT<T> tw_get(const TableTwiddles<T, N>& tw, int, int s, int L, int i, int j) {
+    return tw.p[TableTwiddles<T, N>::off(s) + (i - 1) * L + j];
+}
+
 template <typename T, int DIR> __device__ __forceinline__ cT<T> twmul(cT<T> a, cT<T> w) {
     return DIR < 0 ? cmul<T>(a, w) : cmulc<T>(a, w);
 }
@@ -130,9 +177,8 @@ template <typename T, int DIR> __device__ __forceinline__ cT<T> twmul(cT<T> a, c
 // lds_line_elems(N) elements.  SYNC must be a block-wide barrier (all lines
 // of the block run the same stages).  ZERO_HI: positions >= N / 2 are known
 // to be zero on entry (pruned first stage).
-template <typename T, int N, int DIR, bool ZERO_HI = false>
-__device__ __forceinline__ void fft_line(cT<T> (&v)[8], cT<T>* __restrict__ lds,
-                                         const LineTwiddles<T, N>& tw, int t)
+template <typename T, int N, int DIR, bool ZERO_HI = false, typename TW = LineTwiddles<T, N>>
+__device__ __forceinline__ void fft_line(cT<T> (&v)[8], cT<T>* __restrict__ lds, const TW& tw, int t)
 {
     using S = FftShape<N>;
     constexpr int TPL = S::TPL;
@@ -142,8 +188,9 @@ __device__ __forceinline__ void fft_line(cT<T> (&v)[8], cT<T>* __restrict__ lds,
     for (int s = 0; s < S::S8; ++s) {
         // radix-8 butterfly b = t: inputs at t + i * TPL = v[i]
         if (s > 0) {
+            const int j = t % L;
 #pragma unroll
-            for (int i = 1; i < 8; ++i) v[i] = twmul<T, DIR>(v[i], tw.w[c + i - 1]);
+            for (int i = 1; i < 8; ++i) v[i] = twmul<T, DIR>(v[i], tw_get<T, N>(tw, c + i - 1, s, L, i, j));
             c += 7;
         }
         if (ZERO_HI && s == 0) {
@@ -182,14 +229,16 @@ __device__ __forceinline__ void fft_line(cT<T> (&v)[8], cT<T>* __restrict__ lds,
         // b + i N/4 = t + (u + 2 i) TPL -> slots u + 2 i
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
+            const int j = (t + u * TPL) % L;
 #pragma unroll
-            for (int i = 1; i < 4; ++i) v[u + 2 * i] = twmul<T, DIR>(v[u + 2 * i], tw.w[c++]);
+            for (int i = 1; i < 4; ++i) v[u + 2 * i] = twmul<T, DIR>(v[u + 2 * i], tw_get<T, N>(tw, c++, S::S8, L, i, j));
             dft4<T, DIR>(v[u], v[u + 2], v[u + 4], v[u + 6]);
         }
     } else if constexpr (S::RL == 2) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            v[u + 4] = twmul<T, DIR>(v[u + 4], tw.w[c++]);
+            const int j = (t + u * TPL) % L;
+            v[u + 4] = twmul<T, DIR>(v[u + 4], tw_get<T, N>(tw, c++, S::S8, L, 1, j));
             dft2<T, DIR>(v[u], v[u + 4]);
         }
     }

@@ -49,7 +49,7 @@ def make_desc(problem: dict, precision: str = "fp32", accumulation: str = "defau
         inclination_deg=problem.get("incl", 90.0), declination_deg=problem.get("decl", 0.0),
         field_nT=problem.get("field_nT", 50000.0), scale=problem.get("scale", 0.0),
         nx_fft=problem.get("nx_fft", 0), ny_fft=problem.get("ny_fft", 0),
-        accumulation=_ACC[accumulation])
+        accumulation=_ACC[accumulation], layer_chunk=problem.get("layer_chunk", 0))
     return d, keep
 
 

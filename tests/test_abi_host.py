@@ -100,8 +100,8 @@ def test_sizes_and_fft_choice(lib):
     h = B.bttb_plan_create(W.gravity_1024(), "fp32")
     sb, wb, nx, ny = B.bttb_plan_query(h, 1)
     assert (nx, ny) == (2048, 2048)       # smallest power of two >= 1000 + 1024 - 1
-    # spectra: 128 layers x 2048 x 1025 complex64, plus twiddle tables
-    assert 128 * 2048 * 1025 * 8 <= sb <= 128 * 2048 * 1025 * 8 + 4 * 2048 * 16 + 4096
+    # spectra: 128 layers x 1024 packed columns x 2048 complex64, plus twiddle tables
+    assert 128 * 2048 * 1024 * 8 <= sb <= 128 * 2048 * 1024 * 8 + 4 * 2048 * 16 + 4096
     sb4, wb4, _, _ = B.bttb_plan_query(h, 4)
     assert sb4 == sb and wb4 > wb
     with pytest.raises(B.BttbError):

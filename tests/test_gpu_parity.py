@@ -246,6 +246,18 @@ def test_multiple_rhs_equal_single(torch_cuda, orc, prec):
         assert np.array_equal(d1, d3[q]) and np.array_equal(t1, t3[q])
 
 
+@pytest.mark.parametrize("chunk", [1, 2, 3])
+def test_layer_chunked_transpose_equals_unchunked(torch_cuda, orc, chunk):
+    torch = torch_cuda
+    pr = EDGE[3]                       # 5 layers: chunks of 1, 2 (ragged) and 3 (ragged)
+    a = _plan(pr, "fp32")
+    b = _plan(dict(pr, layer_chunk=chunk), "fp32")
+    v = W.normal_data(pr, 66, nrhs=2)
+    _, ta = _products(torch, a, W.normal_model(pr, 65, nrhs=2), v)
+    _, tb = _products(torch, b, W.normal_model(pr, 65, nrhs=2), v)
+    assert np.array_equal(ta, tb)
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
 def test_adjoint_identity(torch_cuda, prec, tol):
     pr = W.magnetic_24()
