@@ -10,6 +10,8 @@ from .plan import (Plan, bttb_debug_generator, bttb_forward, bttb_forward_profil
                    bttb_kernel_generate, bttb_plan_create, bttb_plan_destroy, bttb_plan_query,
                    bttb_transpose, bttb_transpose_profiled)
 
-__all__ = ["Plan", "BttbError", "bttb_plan_create", "bttb_plan_destroy", "bttb_plan_query",
+from .autograd import BTTBForward, BTTBTranspose, bttb_matvec, bttb_rmatvec  # noqa: F401
+
+__all__ = ["Plan", "BTTBForward", "BTTBTranspose", "bttb_matvec", "bttb_rmatvec", "BttbError", "bttb_plan_create", "bttb_plan_destroy", "bttb_plan_query",
            "bttb_kernel_generate", "bttb_forward", "bttb_transpose", "bttb_forward_profiled",
            "bttb_transpose_profiled", "bttb_debug_generator", "load"]
