@@ -149,6 +149,47 @@ bttb_status bttb_forward(bttb_plan_t plan, const void* spectra, const void* m, v
 bttb_status bttb_transpose(bttb_plan_t plan, const void* spectra, const void* r, void* mt,
                            int32_t nrhs, void* workspace, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batches: many problems (uneven sizes, gravity and magnetic mixed, one
+ * precision) run together.  Every stage of the products is launched once per
+ * transform length with a work table covering all problems of that length,
+ * and the whole sequence of all problems is captured into one HIP graph, so a
+ * run is a single graph launch.  The graph is rebuilt only when the pointers
+ * or right-hand-side counts of a run differ from the previous run's.
+ * ------------------------------------------------------------------------ */
+typedef struct bttb_batch_s* bttb_batch_t;
+
+/* Per-problem inputs of a batch run (all device pointers, caller-owned).
+ * A NULL forward (m, d) or transpose (r, mt) pair skips that product for this
+ * problem; layouts as for bttb_forward / bttb_transpose. */
+typedef struct {
+    const void* spectra;       /* generated spectra of the plan                 */
+    const void* m;             /* [nrhs][nz][ny][nx]                            */
+    void* d;                   /* [nrhs][sy][sx]                                */
+    const void* r;             /* [nrhs][sy][sx]                                */
+    void* mt;                  /* [nrhs][nz][ny][nx]                            */
+    int32_t nrhs;              /* 1 .. max_nrhs                                 */
+} bttb_batch_io;
+
+/* Group nplans plans (not owned; they must outlive the batch) for runs with
+ * at most max_nrhs right-hand sides per problem.  All plans must have the
+ * same precision.  Creates a non-blocking stream (default priority) used for
+ * graph capture.  Errors: NULL_POINTER, INVALID_VALUE, HIP. */
+bttb_status bttb_batch_create(const bttb_plan_t* plans, int32_t nplans, int32_t max_nrhs,
+                              bttb_batch_t* out);
+
+/* Workspace bytes a run needs (device, 256-byte aligned). */
+bttb_status bttb_batch_query(bttb_batch_t batch, size_t* workspace_bytes);
+
+/* Enqueue the products of every problem on `stream` as one graph launch.
+ * io: host array of nplans entries.  Errors: NULL_POINTER, INVALID_VALUE,
+ * WORKSPACE_TOO_SMALL, HIP.  Calls on one batch must not overlap. */
+bttb_status bttb_batch_run(bttb_batch_t batch, const bttb_batch_io* io, void* workspace,
+                           size_t ws_bytes, void* stream);
+
+/* Release the graph, the capture stream and the batch (NULL accepted). */
+bttb_status bttb_batch_destroy(bttb_batch_t batch);
+
 /* Profiling hooks: the same work as bttb_forward / bttb_transpose, with HIP
  * events recorded on the stream around each of the three kernels (row
  * transform, column transform with the depth multiply-accumulate, output row

@@ -19,7 +19,13 @@ BTTB_ACC_DEFAULT, BTTB_ACC_PLAIN, BTTB_ACC_TWOSUM, BTTB_ACC_WIDE = 0, 1, 2, 3
 #: every symbol include/bttb.h declares
 EXPORTS = ["bttb_plan_create", "bttb_plan_destroy", "bttb_plan_query", "bttb_kernel_generate",
            "bttb_forward", "bttb_transpose", "bttb_forward_profiled", "bttb_transpose_profiled",
-           "bttb_debug_generator", "bttb_status_string", "bttb_last_error"]
+           "bttb_debug_generator", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
+           "bttb_batch_destroy", "bttb_status_string", "bttb_last_error"]
+
+
+class BatchIO(ctypes.Structure):
+    _fields_ = [("spectra", ctypes.c_void_p), ("m", ctypes.c_void_p), ("d", ctypes.c_void_p),
+                ("r", ctypes.c_void_p), ("mt", ctypes.c_void_p), ("nrhs", ctypes.c_int32)]
 
 
 class ProblemDesc(ctypes.Structure):
@@ -67,13 +73,18 @@ def load(path: str | None = None) -> ctypes.CDLL:
     L.bttb_forward_profiled.argtypes = [vp, vp, vp, vp, i32, vp, sz, vp, ctypes.POINTER(ctypes.c_float)]
     L.bttb_transpose_profiled.argtypes = [vp, vp, vp, vp, i32, vp, sz, vp, ctypes.POINTER(ctypes.c_float)]
     L.bttb_debug_generator.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), vp, sz, vp]
+    L.bttb_batch_create.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp)]
+    L.bttb_batch_query.argtypes = [vp, ctypes.POINTER(sz)]
+    L.bttb_batch_run.argtypes = [vp, ctypes.POINTER(BatchIO), vp, sz, vp]
+    L.bttb_batch_destroy.argtypes = [vp]
     L.bttb_status_string.argtypes = [ctypes.c_int]
     L.bttb_status_string.restype = ctypes.c_char_p
     L.bttb_last_error.argtypes = []
     L.bttb_last_error.restype = ctypes.c_char_p
     for name in ["bttb_plan_create", "bttb_plan_destroy", "bttb_plan_query", "bttb_kernel_generate",
                  "bttb_forward", "bttb_transpose", "bttb_forward_profiled", "bttb_transpose_profiled",
-                 "bttb_debug_generator"]:
+                 "bttb_debug_generator", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
+                 "bttb_batch_destroy"]:
         getattr(L, name).restype = ctypes.c_int
     _handle = L
     return L

@@ -227,9 +227,13 @@ bttb_status run_generate(const bttb_plan_s* P, char* spec, char* ws, hipStream_t
         const int nl = std::min(P->gen_batch, P->nz - r0);
         const GenParams g = gen_params(P, r0, nl);
         if ((st = hip_check(launch_generate(g, r0, nl, g64, s), "generate")) != BTTB_OK) return st;
-        if ((st = hip_check(launch_rows_r2c<double, double>(P->Nx, g64, (int64_t)P->Nx * P->Ny, P->Nx, P->Nx,
-                                                            P->Ny, nl, w64, (int64_t)P->ncols * P->Ny, P->Ny,
-                                                            tw64x, s), "generator rows")) != BTTB_OK)
+        RowJobs rj{};
+        rj.njobs = 1;
+        rj.j[0] = RowJob{g64, w64, (int64_t)P->Nx * P->Ny, P->Nx, (int64_t)P->ncols * P->Ny, P->Ny,
+                         P->Nx, P->Ny, 0, 0};
+        rj.j[0].bpb = (P->Ny + row_group_rows<double>(P->Nx) - 1) / row_group_rows<double>(P->Nx);
+        rj.total = rj.j[0].bpb * nl;
+        if ((st = hip_check(launch_rows_r2c<double, double>(P->Nx, rj, tw64x, s), "generator rows")) != BTTB_OK)
             return st;
         if ((st = hip_check(launch_cols_spec<T>(P->Ny, w64, P->ncols, nl, out, r0, inv, tw64y, s),
                             "generator columns")) != BTTB_OK)
@@ -239,92 +243,226 @@ bttb_status run_generate(const bttb_plan_s* P, char* spec, char* ws, hipStream_t
 }
 
 // ev: optional array of 4 events recorded before the first kernel and after
-// each of the three kernels (profiling entry points only)
+// each of the three stages (profiling entry points only)
 bttb_status record(hipEvent_t* ev, int k, hipStream_t s)
 {
     if (!ev) return BTTB_OK;
     return hip_check(hipEventRecord(ev[k], s), "event record");
 }
 
-template <typename T>
-bttb_status run_forward(const bttb_plan_s* P, const char* spec, const T* m, T* d, int nrhs, char* ws,
-                        hipStream_t s, hipEvent_t* ev = nullptr)
+// One product of one plan in a launch sequence.
+struct Item {
+    const bttb_plan_s* P;
+    const char* spec;
+    const void* in;   // m (forward) or r (transpose)
+    void* out;        // d (forward) or G^T r (transpose)
+    int nrhs;
+    char* ws;         // this item's workspace (layout ws_layout(P, nrhs))
+};
+
+// Launch `jobs` (all of one transform length) in tables of at most MAX_JOBS.
+template <typename JobT, typename TableT, typename Launch>
+bttb_status launch_tables(const std::vector<JobT>& jobs, const std::vector<int>& work, Launch&& launch,
+                          const char* what)
 {
-    const WsLayout L = ws_layout(P, nrhs);
-    cT<T>* X = (cT<T>*)(ws + L.fwd_x);
-    cT<T>* Y = (cT<T>*)(ws + L.fwd_y);
-    const cT<T>* twx = (const cT<T>*)(spec + P->off_twx);
-    const cT<T>* twy = (const cT<T>*)(spec + P->off_twy);
-    const cT<T>* sp = (const cT<T>*)(spec + P->off_spec);
+    for (size_t a = 0; a < jobs.size(); a += MAX_JOBS) {
+        TableT tab{};
+        int total = 0;
+        for (size_t k = a; k < jobs.size() && k < a + MAX_JOBS; ++k) {
+            tab.j[tab.njobs] = jobs[k];
+            tab.j[tab.njobs].begin = total;
+            total += work[k];
+            ++tab.njobs;
+        }
+        tab.total = total;
+        bttb_status st = hip_check(launch(tab), what);
+        if (st != BTTB_OK) return st;
+    }
+    return BTTB_OK;
+}
+
+// row jobs of one stage, grouped by transform length N (the key)
+template <typename T>
+struct RowStage {
+    std::vector<int> keys;
+    std::vector<std::vector<RowJob>> jobs;
+    std::vector<std::vector<int>> work;
+    std::vector<const cT<T>*> tw;
+    void add(int N, const cT<T>* twp, const RowJob& j, int nbatch)
+    {
+        size_t g = 0;
+        while (g < keys.size() && keys[g] != N) ++g;
+        if (g == keys.size()) { keys.push_back(N); jobs.emplace_back(); work.emplace_back(); tw.push_back(twp); }
+        RowJob jj = j;
+        jj.bpb = (j.nrows + row_group_rows<T>(N) - 1) / row_group_rows<T>(N);
+        jobs[g].push_back(jj);
+        work[g].push_back(jj.bpb * nbatch);
+    }
+};
+
+template <typename T>
+struct ColStage {
+    std::vector<int> keys;   // N * 4 + acc
+    std::vector<std::vector<ColJob>> jobs;
+    std::vector<std::vector<int>> work;
+    std::vector<const cT<T>*> tw;
+    void add(int N, int acc, const cT<T>* twp, const ColJob& j)
+    {
+        const int key = N * 4 + acc;
+        size_t g = 0;
+        while (g < keys.size() && keys[g] != key) ++g;
+        if (g == keys.size()) { keys.push_back(key); jobs.emplace_back(); work.emplace_back(); tw.push_back(twp); }
+        ColJob jj = j;
+        jj.nbx = (j.ncols + col_block_lines(N) - 1) / col_block_lines(N);
+        jobs[g].push_back(jj);
+        work[g].push_back(jj.nbx * j.nrhs);   // one right-hand side per block
+    }
+};
+
+template <typename TI, typename T>
+bttb_status run_rows_r2c(const RowStage<T>& st, hipStream_t s)
+{
+    for (size_t g = 0; g < st.keys.size(); ++g) {
+        const int N = st.keys[g];
+        const cT<T>* tw = st.tw[g];
+        bttb_status r = launch_tables<RowJob, RowJobs>(st.jobs[g], st.work[g],
+            [&](const RowJobs& t) { return launch_rows_r2c<TI, T>(N, t, tw, s); }, "row transforms");
+        if (r != BTTB_OK) return r;
+    }
+    return BTTB_OK;
+}
+
+template <typename T>
+bttb_status run_rows_c2r(const RowStage<T>& st, hipStream_t s)
+{
+    for (size_t g = 0; g < st.keys.size(); ++g) {
+        const int N = st.keys[g];
+        const cT<T>* tw = st.tw[g];
+        bttb_status r = launch_tables<RowJob, RowJobs>(st.jobs[g], st.work[g],
+            [&](const RowJobs& t) { return launch_rows_c2r<T>(N, t, tw, s); }, "output row transforms");
+        if (r != BTTB_OK) return r;
+    }
+    return BTTB_OK;
+}
+
+template <typename T>
+bttb_status run_cols(const ColStage<T>& st, bool fwd, hipStream_t s)
+{
+    for (size_t g = 0; g < st.keys.size(); ++g) {
+        const int N = st.keys[g] / 4, acc = st.keys[g] % 4;
+        const cT<T>* tw = st.tw[g];
+        bttb_status r = launch_tables<ColJob, ColJobs>(st.jobs[g], st.work[g], [&](const ColJobs& t) {
+            if (!fwd) return launch_cols_tr<T>(N, t, tw, s);
+            if constexpr (sizeof(T) == 8) return launch_cols_fwd<T, ACC_PLAIN>(N, t, tw, s);
+            else {
+                if (acc == ACC_PLAIN) return launch_cols_fwd<T, ACC_PLAIN>(N, t, tw, s);
+                if (acc == ACC_TWOSUM) return launch_cols_fwd<T, ACC_TWOSUM>(N, t, tw, s);
+                return launch_cols_fwd<T, ACC_WIDE>(N, t, tw, s);
+            }
+        }, fwd ? "forward columns" : "transpose columns");
+        if (r != BTTB_OK) return r;
+    }
+    return BTTB_OK;
+}
+
+template <typename T> const cT<T>* tw_x(const bttb_plan_s* P, const char* spec) { return (const cT<T>*)(spec + P->off_twx); }
+template <typename T> const cT<T>* tw_y(const bttb_plan_s* P, const char* spec) { return (const cT<T>*)(spec + P->off_twy); }
+
+// forward products of every item: rows of m -> X; columns with the depth
+// multiply-accumulate -> Y; rows of Y -> d
+template <typename T>
+bttb_status run_forward(const std::vector<Item>& items, hipStream_t s, hipEvent_t* ev = nullptr)
+{
+    RowStage<T> r1, r3;
+    ColStage<T> c2;
+    for (const Item& it : items) {
+        const bttb_plan_s* P = it.P;
+        const WsLayout L = ws_layout(P, it.nrhs);
+        cT<T>* X = (cT<T>*)(it.ws + L.fwd_x);
+        cT<T>* Y = (cT<T>*)(it.ws + L.fwd_y);
+        r1.add(P->Nx, tw_x<T>(P, it.spec),
+               RowJob{it.in, X, (int64_t)P->nx * P->ny, P->nx, (int64_t)P->ncols * P->ny, P->ny, P->nx, P->ny, 0, 0},
+               it.nrhs * P->nz);
+        c2.add(P->Ny, P->acc, tw_y<T>(P, it.spec),
+               ColJob{X, it.spec + P->off_spec, Y, P->ny, P->sy, P->ny, P->sy, 0, P->nz, P->ncols, it.nrhs, 0, 0});
+        r3.add(P->Nx, tw_x<T>(P, it.spec),
+               RowJob{Y, it.out, (int64_t)P->ncols * P->sy, P->sy, (int64_t)P->sx * P->sy, P->sx, P->sx, P->sy, 0, 0},
+               it.nrhs);
+    }
     bttb_status st;
     if ((st = record(ev, 0, s)) != BTTB_OK) return st;
-    if ((st = hip_check(launch_rows_r2c<T, T>(P->Nx, m, (int64_t)P->nx * P->ny, P->nx, P->nx, P->ny,
-                                              nrhs * P->nz, X, (int64_t)P->ncols * P->ny, P->ny, twx, s),
-                        "forward rows")) != BTTB_OK)
-        return st;
+    if ((st = run_rows_r2c<T, T>(r1, s)) != BTTB_OK) return st;
     if ((st = record(ev, 1, s)) != BTTB_OK) return st;
-    hipError_t e;
-    if constexpr (sizeof(T) == 8) {
-        e = launch_cols_fwd<T, ACC_PLAIN>(P->Ny, X, P->ny, P->ny, P->nz, P->ncols, sp, Y, P->sy, P->sy, nrhs,
-                                          twy, s);
-    } else {
-        if (P->acc == ACC_PLAIN)
-            e = launch_cols_fwd<T, ACC_PLAIN>(P->Ny, X, P->ny, P->ny, P->nz, P->ncols, sp, Y, P->sy, P->sy,
-                                              nrhs, twy, s);
-        else if (P->acc == ACC_TWOSUM)
-            e = launch_cols_fwd<T, ACC_TWOSUM>(P->Ny, X, P->ny, P->ny, P->nz, P->ncols, sp, Y, P->sy, P->sy,
-                                               nrhs, twy, s);
-        else
-            e = launch_cols_fwd<T, ACC_WIDE>(P->Ny, X, P->ny, P->ny, P->nz, P->ncols, sp, Y, P->sy, P->sy,
-                                             nrhs, twy, s);
-    }
-    if ((st = hip_check(e, "forward columns")) != BTTB_OK) return st;
+    if ((st = run_cols<T>(c2, true, s)) != BTTB_OK) return st;
     if ((st = record(ev, 2, s)) != BTTB_OK) return st;
-    if ((st = hip_check(launch_rows_c2r<T>(P->Nx, Y, (int64_t)P->ncols * P->sy, P->sy, P->sy, nrhs, d,
-                                           (int64_t)P->sx * P->sy, P->sx, P->sx, twx, s),
-                        "forward output rows")) != BTTB_OK)
-        return st;
+    if ((st = run_rows_c2r<T>(r3, s)) != BTTB_OK) return st;
+    return record(ev, 3, s);
+}
+
+// transpose products of every item: rows of r -> R; then per pass of
+// layer_chunk layers: columns (R^ once per column, conj(T^_r) R^, inverse)
+// -> Z; rows of Z -> G^T r
+template <typename T>
+bttb_status run_transpose(const std::vector<Item>& items, hipStream_t s, hipEvent_t* ev = nullptr)
+{
+    RowStage<T> r1;
+    int rounds = 0;
+    for (const Item& it : items) {
+        const bttb_plan_s* P = it.P;
+        const WsLayout L = ws_layout(P, it.nrhs);
+        r1.add(P->Nx, tw_x<T>(P, it.spec),
+               RowJob{it.in, it.ws + L.tr_r, (int64_t)P->sx * P->sy, P->sx, (int64_t)P->ncols * P->sy, P->sy,
+                      P->sx, P->sy, 0, 0},
+               it.nrhs);
+        rounds = std::max(rounds, (P->nz + P->tr_chunk - 1) / P->tr_chunk);
+    }
+    bttb_status st;
+    if ((st = record(ev, 0, s)) != BTTB_OK) return st;
+    if ((st = run_rows_r2c<T, T>(r1, s)) != BTTB_OK) return st;
+    if ((st = record(ev, 1, s)) != BTTB_OK) return st;
+    for (int c = 0; c < rounds; ++c) {
+        ColStage<T> c2;
+        RowStage<T> r3;
+        for (const Item& it : items) {
+            const bttb_plan_s* P = it.P;
+            const int r0 = c * P->tr_chunk;
+            if (r0 >= P->nz) continue;
+            const int nl = std::min(P->tr_chunk, P->nz - r0);
+            const WsLayout L = ws_layout(P, it.nrhs);
+            const cT<T>* R = (const cT<T>*)(it.ws + L.tr_r);
+            cT<T>* Z = (cT<T>*)(it.ws + L.tr_z);
+            c2.add(P->Ny, 0, tw_y<T>(P, it.spec),
+                   ColJob{R, it.spec + P->off_spec, Z, P->sy, P->ny, P->sy, P->ny, r0, nl, P->ncols, it.nrhs, 0, 0});
+            T* out = (T*)it.out;
+            if (nl == P->nz) {
+                r3.add(P->Nx, tw_x<T>(P, it.spec),
+                       RowJob{Z, out, (int64_t)P->ncols * P->ny, P->ny, (int64_t)P->nx * P->ny, P->nx, P->nx, P->ny,
+                              0, 0},
+                       it.nrhs * P->nz);
+            } else {
+                for (int q = 0; q < it.nrhs; ++q)
+                    r3.add(P->Nx, tw_x<T>(P, it.spec),
+                           RowJob{Z + (size_t)q * nl * P->ncols * P->ny, out + ((size_t)q * P->nz + r0) * P->nx * P->ny,
+                                  (int64_t)P->ncols * P->ny, P->ny, (int64_t)P->nx * P->ny, P->nx, P->nx, P->ny, 0, 0},
+                           nl);
+            }
+        }
+        if ((st = run_cols<T>(c2, false, s)) != BTTB_OK) return st;
+        if (rounds == 1 && (st = record(ev, 2, s)) != BTTB_OK) return st;
+        if ((st = run_rows_c2r<T>(r3, s)) != BTTB_OK) return st;
+    }
+    // passes interleave the two kernels: their joint time is reported as the
+    // column kernel's, the row kernel's as 0
+    if (rounds > 1 && (st = record(ev, 2, s)) != BTTB_OK) return st;
     return record(ev, 3, s);
 }
 
 template <typename T>
-bttb_status run_transpose(const bttb_plan_s* P, const char* spec, const T* r, T* mt, int nrhs, char* ws,
-                          hipStream_t s, hipEvent_t* ev = nullptr)
+bttb_status run_single(bool fwd, const bttb_plan_s* P, const char* spec, const void* in, void* out, int nrhs,
+                       char* ws, hipStream_t s, hipEvent_t* ev = nullptr)
 {
-    const WsLayout L = ws_layout(P, nrhs);
-    cT<T>* R = (cT<T>*)(ws + L.tr_r);
-    cT<T>* Z = (cT<T>*)(ws + L.tr_z);
-    const cT<T>* twx = (const cT<T>*)(spec + P->off_twx);
-    const cT<T>* twy = (const cT<T>*)(spec + P->off_twy);
-    const cT<T>* sp = (const cT<T>*)(spec + P->off_spec);
-    bttb_status st;
-    if ((st = record(ev, 0, s)) != BTTB_OK) return st;
-    if ((st = hip_check(launch_rows_r2c<T, T>(P->Nx, r, (int64_t)P->sx * P->sy, P->sx, P->sx, P->sy, nrhs, R,
-                                              (int64_t)P->ncols * P->sy, P->sy, twx, s),
-                        "transpose rows")) != BTTB_OK)
-        return st;
-    if ((st = record(ev, 1, s)) != BTTB_OK) return st;
-    const int LC = P->tr_chunk;
-    for (int r0 = 0; r0 < P->nz; r0 += LC) {
-        const int nl = std::min(LC, P->nz - r0);
-        if ((st = hip_check(launch_cols_tr<T>(P->Ny, R, P->sy, P->sy, r0, nl, P->ncols, sp, Z, P->ny, P->ny, nrhs,
-                                              twy, s),
-                            "transpose columns")) != BTTB_OK)
-            return st;
-        if (LC == P->nz && (st = record(ev, 2, s)) != BTTB_OK) return st;
-        for (int q = 0; q < nrhs; ++q) {
-            if ((st = hip_check(launch_rows_c2r<T>(P->Nx, Z + (size_t)q * nl * P->ncols * P->ny,
-                                                   (int64_t)P->ncols * P->ny, P->ny, P->ny, nl,
-                                                   mt + ((size_t)q * P->nz + r0) * P->nx * P->ny,
-                                                   (int64_t)P->nx * P->ny, P->nx, P->nx, twx, s),
-                                "transpose output rows")) != BTTB_OK)
-                return st;
-        }
-    }
-    // chunked passes interleave the two kernels: their joint time is
-    // reported as the column kernel's, the row kernel's as 0
-    if (LC < P->nz && (st = record(ev, 2, s)) != BTTB_OK) return st;
-    return record(ev, 3, s);
+    std::vector<Item> items{Item{P, spec, in, out, nrhs, ws}};
+    return fwd ? run_forward<T>(items, s, ev) : run_transpose<T>(items, s, ev);
 }
 
 }  // namespace
@@ -411,10 +549,8 @@ bttb_status bttb_forward(bttb_plan_t plan, const void* spectra, const void* m, v
         bttb_status st = check_product_args(plan, spectra, m, d, nrhs, workspace, ws_bytes);
         if (st != BTTB_OK) return st;
         hipStream_t s = (hipStream_t)stream;
-        return plan->fp64 ? run_forward<double>(plan, (const char*)spectra, (const double*)m, (double*)d, nrhs,
-                                                (char*)workspace, s)
-                          : run_forward<float>(plan, (const char*)spectra, (const float*)m, (float*)d, nrhs,
-                                               (char*)workspace, s);
+        return plan->fp64 ? run_single<double>(true, plan, (const char*)spectra, m, d, nrhs, (char*)workspace, s)
+                          : run_single<float>(true, plan, (const char*)spectra, m, d, nrhs, (char*)workspace, s);
     } catch (...) {
         return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_forward");
     }
@@ -428,10 +564,8 @@ bttb_status bttb_transpose(bttb_plan_t plan, const void* spectra, const void* r,
         bttb_status st = check_product_args(plan, spectra, r, mt, nrhs, workspace, ws_bytes);
         if (st != BTTB_OK) return st;
         hipStream_t s = (hipStream_t)stream;
-        return plan->fp64 ? run_transpose<double>(plan, (const char*)spectra, (const double*)r, (double*)mt, nrhs,
-                                                  (char*)workspace, s)
-                          : run_transpose<float>(plan, (const char*)spectra, (const float*)r, (float*)mt, nrhs,
-                                                 (char*)workspace, s);
+        return plan->fp64 ? run_single<double>(false, plan, (const char*)spectra, r, mt, nrhs, (char*)workspace, s)
+                          : run_single<float>(false, plan, (const char*)spectra, r, mt, nrhs, (char*)workspace, s);
     } catch (...) {
         return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_transpose");
     }
@@ -449,12 +583,8 @@ static bttb_status profiled(bool fwd, bttb_plan_t plan, const void* spectra, con
     if (st == BTTB_OK) {
         const char* sp = (const char*)spectra;
         char* ws = (char*)workspace;
-        if (fwd)
-            st = plan->fp64 ? run_forward<double>(plan, sp, (const double*)in, (double*)out, nrhs, ws, s, ev)
-                            : run_forward<float>(plan, sp, (const float*)in, (float*)out, nrhs, ws, s, ev);
-        else
-            st = plan->fp64 ? run_transpose<double>(plan, sp, (const double*)in, (double*)out, nrhs, ws, s, ev)
-                            : run_transpose<float>(plan, sp, (const float*)in, (float*)out, nrhs, ws, s, ev);
+        st = plan->fp64 ? run_single<double>(fwd, plan, sp, in, out, nrhs, ws, s, ev)
+                        : run_single<float>(fwd, plan, sp, in, out, nrhs, ws, s, ev);
     }
     if (st == BTTB_OK) st = hip_check(hipEventSynchronize(ev[3]), "event synchronize");
     for (int k = 0; k < 3 && st == BTTB_OK; ++k)
@@ -507,6 +637,145 @@ bttb_status bttb_debug_generator(bttb_plan_t plan, int32_t layer, double* host_o
     } catch (...) {
         return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_debug_generator");
     }
+}
+
+}  // extern "C"
+
+struct bttb_batch_s {
+    std::vector<const bttb_plan_s*> plans;
+    int max_nrhs = 1;
+    bool fp64 = false;
+    std::vector<size_t> ws_off;
+    size_t ws_total = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uintptr_t> key;     // pointers and counts of the captured run
+};
+
+namespace {
+
+void batch_release_graph(bttb_batch_s* B)
+{
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    B->exec = nullptr;
+    B->graph = nullptr;
+    B->key.clear();
+}
+
+template <typename T>
+bttb_status batch_enqueue(bttb_batch_s* B, const bttb_batch_io* io, char* ws, hipStream_t s)
+{
+    std::vector<Item> fwd, tr;
+    for (size_t k = 0; k < B->plans.size(); ++k) {
+        const bttb_plan_s* P = B->plans[k];
+        char* w = ws + B->ws_off[k];
+        if (io[k].m) fwd.push_back(Item{P, (const char*)io[k].spectra, io[k].m, io[k].d, io[k].nrhs, w});
+        if (io[k].r) tr.push_back(Item{P, (const char*)io[k].spectra, io[k].r, io[k].mt, io[k].nrhs, w});
+    }
+    bttb_status st = BTTB_OK;
+    if (!fwd.empty()) st = run_forward<T>(fwd, s);
+    // a problem with both products reuses its workspace: the transpose of the
+    // batch runs after every forward (stream order)
+    if (st == BTTB_OK && !tr.empty()) st = run_transpose<T>(tr, s);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+bttb_status bttb_batch_create(const bttb_plan_t* plans, int32_t nplans, int32_t max_nrhs, bttb_batch_t* out)
+{
+    try {
+        g_last_error.clear();
+        if (!plans || !out) return fail(BTTB_ERR_NULL_POINTER, "plans and out must not be NULL");
+        *out = nullptr;
+        if (nplans < 1 || max_nrhs < 1) return fail(BTTB_ERR_INVALID_VALUE, "nplans and max_nrhs must be >= 1");
+        bttb_batch_s* B = new (std::nothrow) bttb_batch_s();
+        if (!B) return fail(BTTB_ERR_INTERNAL, "out of host memory");
+        B->max_nrhs = max_nrhs;
+        for (int k = 0; k < nplans; ++k) {
+            if (!plans[k]) { delete B; return fail(BTTB_ERR_NULL_POINTER, "plans[k] must not be NULL"); }
+            if (k > 0 && plans[k]->fp64 != plans[0]->fp64) {
+                delete B;
+                return fail(BTTB_ERR_INVALID_VALUE, "all plans of a batch must have the same precision");
+            }
+            B->plans.push_back(plans[k]);
+            B->ws_off.push_back(B->ws_total);
+            B->ws_total = align_up(B->ws_total + ws_layout(plans[k], max_nrhs).total);
+        }
+        B->fp64 = plans[0]->fp64;
+        bttb_status st = hip_check(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking), "stream create");
+        if (st != BTTB_OK) { delete B; return st; }
+        *out = B;
+        return BTTB_OK;
+    } catch (...) {
+        return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_batch_create");
+    }
+}
+
+bttb_status bttb_batch_query(bttb_batch_t batch, size_t* workspace_bytes)
+{
+    g_last_error.clear();
+    if (!batch || !workspace_bytes) return fail(BTTB_ERR_NULL_POINTER, "batch and workspace_bytes must not be NULL");
+    *workspace_bytes = batch->ws_total;
+    return BTTB_OK;
+}
+
+bttb_status bttb_batch_run(bttb_batch_t B, const bttb_batch_io* io, void* workspace, size_t ws_bytes, void* stream)
+{
+    try {
+        g_last_error.clear();
+        if (!B || !io || !workspace) return fail(BTTB_ERR_NULL_POINTER, "batch, io and workspace must not be NULL");
+        if (ws_bytes < B->ws_total) return fail(BTTB_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than bttb_batch_query reports");
+        if (!aligned(workspace, kAlign)) return fail(BTTB_ERR_INVALID_VALUE, "workspace must be 256-byte aligned");
+        std::vector<uintptr_t> key{(uintptr_t)workspace, (uintptr_t)ws_bytes};
+        for (size_t k = 0; k < B->plans.size(); ++k) {
+            const bttb_batch_io& e = io[k];
+            const size_t esz = B->plans[k]->esz;
+            if (!e.spectra) return fail(BTTB_ERR_NULL_POINTER, "io[k].spectra must not be NULL");
+            if ((!e.m) != (!e.d) || (!e.r) != (!e.mt))
+                return fail(BTTB_ERR_NULL_POINTER, "io[k]: m and d (and r and mt) must be both set or both NULL");
+            if (e.nrhs < 1 || e.nrhs > B->max_nrhs) return fail(BTTB_ERR_INVALID_VALUE, "io[k].nrhs out of range");
+            if (!aligned(e.spectra, kAlign) || !aligned(e.m, esz) || !aligned(e.d, esz) || !aligned(e.r, esz) ||
+                !aligned(e.mt, esz))
+                return fail(BTTB_ERR_INVALID_VALUE, "misaligned buffer in io[k]");
+            for (uintptr_t v : {(uintptr_t)e.spectra, (uintptr_t)e.m, (uintptr_t)e.d, (uintptr_t)e.r,
+                                (uintptr_t)e.mt, (uintptr_t)e.nrhs})
+                key.push_back(v);
+        }
+        if (!B->exec || key != B->key) {
+            batch_release_graph(B);
+            bttb_status st = hip_check(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+            if (st != BTTB_OK) return st;
+            st = B->fp64 ? batch_enqueue<double>(B, io, (char*)workspace, B->cap)
+                         : batch_enqueue<float>(B, io, (char*)workspace, B->cap);
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(B->cap, &g);
+            if (st != BTTB_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+            if ((st = hip_check(e, "end capture")) != BTTB_OK) return st;
+            B->graph = g;
+            if ((st = hip_check(hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0), "graph instantiate")) != BTTB_OK) {
+                batch_release_graph(B);
+                return st;
+            }
+            B->key = key;
+        }
+        return hip_check(hipGraphLaunch(B->exec, (hipStream_t)stream), "graph launch");
+    } catch (...) {
+        return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_batch_run");
+    }
+}
+
+bttb_status bttb_batch_destroy(bttb_batch_t B)
+{
+    if (!B) return BTTB_OK;
+    batch_release_graph(B);
+    if (B->cap) (void)hipStreamDestroy(B->cap);
+    delete B;
+    return BTTB_OK;
 }
 
 const char* bttb_status_string(bttb_status s)

@@ -22,6 +22,43 @@ struct GenParams {
     MagWeights w;
 };
 
+// Work tables.  A launch of a row or column kernel processes every job of
+// its table (one job per problem instance / right-hand-side batch, all with
+// the same transform length); the table is passed by value as a kernel
+// argument, so no device memory holds it.
+constexpr int MAX_JOBS = 32;
+
+struct RowJob {
+    const void* in;       // real rows (r2c) or packed half spectra (c2r)
+    void* out;            // packed half spectra (r2c) or real rows (c2r)
+    int64_t in_bs, in_ld; // batch and row/column strides of the input (elements)
+    int64_t out_bs, out_ld;
+    int nv;               // r2c: valid input length of a row; c2r: output length
+    int nrows;            // rows per batch
+    int bpb;              // row groups per batch
+    int begin;            // first global row-group index of this job
+};
+struct RowJobs {
+    RowJob j[MAX_JOBS];
+    int njobs, total;     // total = row groups of all jobs
+};
+
+struct ColJob {
+    const void* a;        // input columns: X (forward) or R (transpose)
+    const void* spec;     // spectra of the job's plan
+    void* b;              // output columns: Y (forward) or Z (transpose)
+    int64_t lda, ldb;     // column strides of a and b (elements)
+    int na, nb;           // valid rows of a (ny or sy), rows written to b (sy or ny)
+    int r0, nl;           // layers [r0, r0 + nl)
+    int ncols, nrhs;
+    int nbx;              // column blocks per right-hand-side block
+    int begin;            // first global block index of this job
+};
+struct ColJobs {
+    ColJob j[MAX_JOBS];
+    int njobs, total;     // total = blocks of all jobs
+};
+
 template <typename T> struct cplx;
 template <> struct cplx<float> { using type = float2; };
 template <> struct cplx<double> { using type = double2; };
@@ -29,24 +66,19 @@ template <typename T> using cT = typename cplx<T>::type;
 
 hipError_t launch_twiddles(double2* t64, float2* t32, int n, hipStream_t s);
 hipError_t launch_generate(const GenParams& P, int r0, int nl, double* out, hipStream_t s);
+// rows per row group and columns per column block of the kernels for length N
+template <typename T> int row_group_rows(int N);
+int col_block_lines(int N);
 template <typename TI, typename T>
-hipError_t launch_rows_r2c(int N, const TI* in, int64_t in_bs, int64_t in_ld, int nvx, int nrows,
-                           int nbatch, cT<T>* out, int64_t out_bs, int64_t out_ld, const cT<T>* tw,
-                           hipStream_t s);
+hipError_t launch_rows_r2c(int N, const RowJobs& jobs, const cT<T>* tw, hipStream_t s);
 template <typename T>
-hipError_t launch_rows_c2r(int N, const cT<T>* in, int64_t in_bs, int64_t in_ld, int nrows,
-                           int nbatch, T* out, int64_t out_bs, int64_t out_ld, int nvx_out,
-                           const cT<T>* tw, hipStream_t s);
+hipError_t launch_rows_c2r(int N, const RowJobs& jobs, const cT<T>* tw, hipStream_t s);
 template <typename T>
 hipError_t launch_cols_spec(int N, const double2* in, int ncols, int nl, cT<T>* spec, int r0,
                             double scale, const double2* tw, hipStream_t s);
 template <typename T, int ACC>
-hipError_t launch_cols_fwd(int N, const cT<T>* X, int64_t ldx, int ny, int nz, int ncols,
-                           const cT<T>* spec, cT<T>* Y, int64_t ldy, int sy, int nrhs,
-                           const cT<T>* tw, hipStream_t s);
+hipError_t launch_cols_fwd(int N, const ColJobs& jobs, const cT<T>* tw, hipStream_t s);
 template <typename T>
-hipError_t launch_cols_tr(int N, const cT<T>* R, int64_t ldr, int sy, int r0, int nl, int ncols,
-                          const cT<T>* spec, cT<T>* Z, int64_t ldz, int ny, int nrhs,
-                          const cT<T>* tw, hipStream_t s);
+hipError_t launch_cols_tr(int N, const ColJobs& jobs, const cT<T>* tw, hipStream_t s);
 
 }  // namespace bttbk

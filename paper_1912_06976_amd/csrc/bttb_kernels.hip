@@ -171,34 +171,45 @@ template <typename T, int N> struct RowCfg {
 // The loads of the next group are issued before the current group is
 // transformed, so memory latency overlaps the FFT.
 
-// in:  batch b, row y, column x at in[b * in_bs + y * in_ld + x], x < nvx valid
-// out: packed half spectra out[b * out_bs + kx * out_ld + y], kx < N/2, y < nrows
+// index of the job whose work range [begin, next begin) contains w
+template <typename JT> __device__ __forceinline__ int find_job(const JT& js, int w)
+{
+    int k = 0;
+    for (int i = 1; i < js.njobs; ++i)
+        if (w >= js.j[i].begin) k = i;
+    return k;
+}
+
+// Row transform, real -> packed half spectra, over every job of the table.
+// Job input: batch b, row y, column x at in[b * in_bs + y * in_ld + x],
+// x < nv valid (zero beyond, up to N); output: packed half spectra at
+// out[b * out_bs + kx * out_ld + y], kx < N/2, y < nrows.
 template <typename TI, typename T, int N>
 __global__ void __launch_bounds__((RowCfg<T, N>::THREADS))
-k_rows_r2c(const TI* __restrict__ in, int64_t in_bs, int64_t in_ld, int nvx, int nrows,
-           cT<T>* __restrict__ out, int64_t out_bs, int64_t out_ld, const cT<T>* __restrict__ tw,
-           int blocks_per_batch, int total)
+k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
 {
     using C = RowCfg<T, N>;
     constexpr int TPL = C::TPL;
     __shared__ cT<T> lds[C::LDS + TableTwiddles<T, N>::size()];
-    const int G = gridDim.x;
+    const int G = gridDim.x, total = jobs.total;
     const int pr = threadIdx.x / TPL, t = threadIdx.x % TPL;
     TableTwiddles<T, N>::build(lds + C::TWO, tw, threadIdx.x, C::THREADS);
     __syncthreads();
     const TableTwiddles<T, N> twl{lds + C::TWO};
     cT<T>* xl = lds + pr * lds_line_elems(N);
     auto load = [&](int g, cT<T> (&v)[8]) {
-        const int b = g / blocks_per_batch;
-        const int ra = (g % blocks_per_batch) * C::RT + 2 * pr, rb = ra + 1;
-        const TI* src = in + (int64_t)b * in_bs;
+        const RowJob& J = jobs.j[find_job(jobs, g)];
+        const int gl = g - J.begin;
+        const int b = gl / J.bpb;
+        const int ra = (gl % J.bpb) * C::RT + 2 * pr, rb = ra + 1;
+        const TI* src = (const TI*)J.in + (int64_t)b * J.in_bs;
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
             const int x = t + m * TPL;
             T a = 0, c = 0;
-            if (x < nvx) {
-                if (ra < nrows) a = (T)src[(int64_t)ra * in_ld + x];
-                if (rb < nrows) c = (T)src[(int64_t)rb * in_ld + x];
+            if (x < J.nv) {
+                if (ra < J.nrows) a = (T)src[(int64_t)ra * J.in_ld + x];
+                if (rb < J.nrows) c = (T)src[(int64_t)rb * J.in_ld + x];
             }
             v[m] = mk<T>(a, c);
         }
@@ -209,9 +220,11 @@ k_rows_r2c(const TI* __restrict__ in, int64_t in_bs, int64_t in_ld, int nvx, int
     for (; g < total; g += G) {
         cT<T> vn[8];
         if (g + G < total) load(g + G, vn);
-        const int b = g / blocks_per_batch;
-        const int row0 = (g % blocks_per_batch) * C::RT;
-        if (nvx <= N / 2) fft_line<T, N, -1, true>(v, xl, twl, t);
+        const RowJob& J = jobs.j[find_job(jobs, g)];
+        const int gl = g - J.begin;
+        const int b = gl / J.bpb;
+        const int row0 = (gl % J.bpb) * C::RT;
+        if (J.nv <= N / 2) fft_line<T, N, -1, true>(v, xl, twl, t);
         else fft_line<T, N, -1, false>(v, xl, twl, t);
         // split Z = FFT(a + i c) into A = FFT(a), C = FFT(c):
         // A[k] = (Z[k] + conj Z[N-k]) / 2, C[k] = (Z[k] - conj Z[N-k]) / (2 i)
@@ -242,31 +255,30 @@ k_rows_r2c(const TI* __restrict__ in, int64_t in_bs, int64_t in_ld, int nvx, int
             lds[k * C::SROW + 2 * pr + 1] = Cc[m];
         }
         __syncthreads();
-        cT<T>* dst = out + (int64_t)b * out_bs;
+        cT<T>* dst = (cT<T>*)J.out + (int64_t)b * J.out_bs;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int e = threadIdx.x + i * C::THREADS;   // HALF * RT = 8 * THREADS
             const int kx = e / C::RT, rr = e % C::RT;
-            if (row0 + rr < nrows) dst[(int64_t)kx * out_ld + row0 + rr] = lds[kx * C::SROW + rr];
+            if (row0 + rr < J.nrows) dst[(int64_t)kx * J.out_ld + row0 + rr] = lds[kx * C::SROW + rr];
         }
 #pragma unroll
         for (int m = 0; m < 8; ++m) v[m] = vn[m];
     }
 }
 
-// in:  packed half spectra in[b * in_bs + kx * in_ld + y], kx < N/2, y < nrows
-// out: out[b * out_bs + y * out_ld + x] for x < nvx_out (real, unnormalised
-//      inverse transform; the 1/(Nx Ny) factor lives in the spectra)
+// Row transform, packed half spectra -> real rows, over every job of the
+// table.  Job input: in[b * in_bs + kx * in_ld + y], kx < N/2, y < nrows;
+// output: out[b * out_bs + y * out_ld + x] for x < nv (real, unnormalised
+// inverse transform; the 1/(Nx Ny) factor lives in the spectra).
 template <typename T, int N>
 __global__ void __launch_bounds__((RowCfg<T, N>::THREADS))
-k_rows_c2r(const cT<T>* __restrict__ in, int64_t in_bs, int64_t in_ld, int nrows,
-           T* __restrict__ out, int64_t out_bs, int64_t out_ld, int nvx_out,
-           const cT<T>* __restrict__ tw, int blocks_per_batch, int total)
+k_rows_c2r(RowJobs jobs, const cT<T>* __restrict__ tw)
 {
     using C = RowCfg<T, N>;
     constexpr int TPL = C::TPL;
     __shared__ cT<T> lds[C::LDS + TableTwiddles<T, N>::size()];
-    const int G = gridDim.x;
+    const int G = gridDim.x, total = jobs.total;
     const int pr = threadIdx.x / TPL, t = threadIdx.x % TPL;
     TableTwiddles<T, N>::build(lds + C::TWO, tw, threadIdx.x, C::THREADS);
     __syncthreads();
@@ -275,14 +287,16 @@ k_rows_c2r(const cT<T>* __restrict__ in, int64_t in_bs, int64_t in_ld, int nrows
     // tile of the packed half spectra of RT rows: HALF * RT = 8 * THREADS
     // elements, element e = threadIdx.x + i THREADS at (kx, row) = (e / RT, e % RT)
     auto load = [&](int g, cT<T> (&tl)[8]) {
-        const int b = g / blocks_per_batch;
-        const int row0 = (g % blocks_per_batch) * C::RT;
-        const cT<T>* src = in + (int64_t)b * in_bs;
+        const RowJob& J = jobs.j[find_job(jobs, g)];
+        const int gl = g - J.begin;
+        const int b = gl / J.bpb;
+        const int row0 = (gl % J.bpb) * C::RT;
+        const cT<T>* src = (const cT<T>*)J.in + (int64_t)b * J.in_bs;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int e = threadIdx.x + i * C::THREADS;
             const int kx = e / C::RT, rr = e % C::RT;
-            tl[i] = (row0 + rr < nrows) ? src[(int64_t)kx * in_ld + row0 + rr] : mk<T>(0, 0);
+            tl[i] = (row0 + rr < J.nrows) ? src[(int64_t)kx * J.in_ld + row0 + rr] : mk<T>(0, 0);
         }
     };
     int g = xcd_order(blockIdx.x, G);
@@ -317,15 +331,17 @@ k_rows_c2r(const cT<T>* __restrict__ in, int64_t in_bs, int64_t in_ld, int nrows
             v[m] = mk<T>(A.x - Cc.y, A.y + Cc.x);
         }
         fft_line<T, N, +1, false>(v, xl, twl, t);   // begins with a barrier
-        const int b = g / blocks_per_batch;
-        const int ra = (g % blocks_per_batch) * C::RT + 2 * pr, rb = ra + 1;
-        T* dst = out + (int64_t)b * out_bs;
+        const RowJob& J = jobs.j[find_job(jobs, g)];
+        const int gl = g - J.begin;
+        const int b = gl / J.bpb;
+        const int ra = (gl % J.bpb) * C::RT + 2 * pr, rb = ra + 1;
+        T* dst = (T*)J.out + (int64_t)b * J.out_bs;
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
             const int x = t + m * TPL;
-            if (x < nvx_out) {
-                if (ra < nrows) dst[(int64_t)ra * out_ld + x] = v[m].x;
-                if (rb < nrows) dst[(int64_t)rb * out_ld + x] = v[m].y;
+            if (x < J.nv) {
+                if (ra < J.nrows) dst[(int64_t)ra * J.out_ld + x] = v[m].x;
+                if (rb < J.nrows) dst[(int64_t)rb * J.out_ld + x] = v[m].y;
             }
         }
     }
@@ -437,23 +453,30 @@ template <int N> __device__ __forceinline__ int mirror_idx(int t, int m) {
     return lpad((N - t - m * (N / 8)) & (N - 1));
 }
 
-// forward: X[((q * nz + r) * ncols + kx) * ldx + y], y < ny (packed row-pass
-// output); Y[(q * ncols + kx) * ldy + y], y < sy
+// Forward column pass over every job of the table (one block per CPW
+// columns of one right-hand-side block of one job).  Job: a = X with
+// X[((q * nz + r) * ncols + kx) * lda + y], y < na = ny (packed row-pass
+// output), nl = nz layers; b = Y with Y[(q * ncols + kx) * ldb + y], y < nb = sy.
 template <typename T, int N, int NR, int ACC>
 __global__ void __launch_bounds__(ColCfg<N>::THREADS, BTTB_COL_WAVES)
-k_cols_fwd_mac(const cT<T>* __restrict__ X, int64_t ldx, int ny, int nz, int ncols,
-               const cT<T>* __restrict__ spec, cT<T>* __restrict__ Y, int64_t ldy, int sy,
-               int nrhs, const cT<T>* __restrict__ tw)
+k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
 {
     using C = ColCfg<N>;
     constexpr int TPL = C::TPL;
     constexpr int LL = lds_line_elems(N);
     __shared__ cT<T> lds[(C::CPW + 1) * LL];
+    const ColJob& J = jobs.j[find_job(jobs, blockIdx.x)];
+    const cT<T>* __restrict__ X = (const cT<T>*)J.a;
+    const cT<T>* __restrict__ spec = (const cT<T>*)J.spec;
+    cT<T>* __restrict__ Y = (cT<T>*)J.b;
+    const int64_t ldx = J.lda, ldy = J.ldb;
+    const int ny = J.na, sy = J.nb, nz = J.nl, ncols = J.ncols, nrhs = J.nrhs;
+    const int lb = blockIdx.x - J.begin, cb = lb % J.nbx;
     const int cl = threadIdx.x / TPL, t = threadIdx.x % TPL;
-    const int col = blockIdx.x * C::CPW + cl;
-    const int q0 = blockIdx.y * NR;
+    const int col = cb * C::CPW + cl;
+    const int q0 = (lb / J.nbx) * NR;
     const bool ok = col < ncols;
-    const bool packed_blk = blockIdx.x == 0;      // block holding column 0
+    const bool packed_blk = cb == 0;              // block holding column 0
     const bool packed = packed_blk && cl == 0;
     cT<T>* xl = lds + cl * LL;
     cT<T>* xs2 = lds + C::CPW * LL;               // second buffer (column 0)
@@ -536,24 +559,30 @@ k_cols_fwd_mac(const cT<T>* __restrict__ X, int64_t ldx, int ny, int nz, int nco
     }
 }
 
-// transpose over layers [r0, r0 + nl): R[(q * ncols + kx) * ldr + y], y < sy
-// (packed row-pass output of the data); Z[((q * nl + r - r0) * ncols + kx) * ldz + y],
-// y < ny
+// Transpose column pass over every job of the table, layers [r0, r0 + nl).
+// Job: a = R with R[(q * ncols + kx) * lda + y], y < na = sy (packed row-pass
+// output of the data); b = Z with Z[((q * nl + r - r0) * ncols + kx) * ldb + y],
+// y < nb = ny.
 template <typename T, int N, int NR>
 __global__ void __launch_bounds__(ColCfg<N>::THREADS, BTTB_COL_WAVES)
-k_cols_tr_mac(const cT<T>* __restrict__ R, int64_t ldr, int sy, int r0, int nl, int ncols,
-              const cT<T>* __restrict__ spec, cT<T>* __restrict__ Z, int64_t ldz, int ny,
-              int nrhs, const cT<T>* __restrict__ tw)
+k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
 {
     using C = ColCfg<N>;
     constexpr int TPL = C::TPL;
     constexpr int LL = lds_line_elems(N);
     __shared__ cT<T> lds[(C::CPW + 1) * LL];
+    const ColJob& J = jobs.j[find_job(jobs, blockIdx.x)];
+    const cT<T>* __restrict__ R = (const cT<T>*)J.a;
+    const cT<T>* __restrict__ spec = (const cT<T>*)J.spec;
+    cT<T>* __restrict__ Z = (cT<T>*)J.b;
+    const int64_t ldr = J.lda, ldz = J.ldb;
+    const int sy = J.na, ny = J.nb, r0 = J.r0, nl = J.nl, ncols = J.ncols, nrhs = J.nrhs;
+    const int lb = blockIdx.x - J.begin, cb = lb % J.nbx;
     const int cl = threadIdx.x / TPL, t = threadIdx.x % TPL;
-    const int col = blockIdx.x * C::CPW + cl;
-    const int q0 = blockIdx.y * NR;
+    const int col = cb * C::CPW + cl;
+    const int q0 = (lb / J.nbx) * NR;
     const bool ok = col < ncols;
-    const bool packed_blk = blockIdx.x == 0;
+    const bool packed_blk = cb == 0;
     const bool packed = packed_blk && cl == 0;
     cT<T>* xl = lds + cl * LL;
     cT<T>* xs2 = lds + C::CPW * LL;
@@ -664,21 +693,35 @@ hipError_t launch_generate(const GenParams& P, int r0, int nl, double* out, hipS
     return hipGetLastError();
 }
 
-template <typename TI, typename T>
-hipError_t launch_rows_r2c(int N, const TI* in, int64_t in_bs, int64_t in_ld, int nvx, int nrows,
-                           int nbatch, cT<T>* out, int64_t out_bs, int64_t out_ld, const cT<T>* tw,
-                           hipStream_t s)
+template <typename T> int row_group_rows(int N)
 {
+#define L_RT(NN) return RowCfg<T, NN>::RT;
+    switch (N) {
+    case 8: L_RT(8) case 16: L_RT(16) case 32: L_RT(32) case 64: L_RT(64) case 128: L_RT(128)
+    case 256: L_RT(256) case 512: L_RT(512) case 1024: L_RT(1024) case 2048: L_RT(2048)
+    case 4096: L_RT(4096) default: return 1;
+    }
+#undef L_RT
+}
+template int row_group_rows<float>(int);
+template int row_group_rows<double>(int);
+
+int col_block_lines(int N)
+{
+    return N / 8 >= 256 ? 1 : 256 / (N / 8);
+}
+
+template <typename TI, typename T>
+hipError_t launch_rows_r2c(int N, const RowJobs& jobs, const cT<T>* tw, hipStream_t s)
+{
+    if (jobs.total <= 0) return hipSuccess;
 #define L_R2C(NN)                                                                          \
     {                                                                                      \
         using C = RowCfg<T, NN>;                                                           \
-        const int bpb = (nrows + C::RT - 1) / C::RT;                                       \
-        const int total = bpb * nbatch;                                                    \
         static int resident = 0;                                                           \
         if (!resident) resident = resident_blocks((const void*)k_rows_r2c<TI, T, NN>, C::THREADS); \
-        const int grid = std::min(total, resident);                                        \
-        hipLaunchKernelGGL((k_rows_r2c<TI, T, NN>), dim3(grid), dim3(C::THREADS), 0, s,    \
-                           in, in_bs, in_ld, nvx, nrows, out, out_bs, out_ld, tw, bpb, total); \
+        hipLaunchKernelGGL((k_rows_r2c<TI, T, NN>), dim3(std::min(jobs.total, resident)),  \
+                           dim3(C::THREADS), 0, s, jobs, tw);                              \
     }
     BTTB_LEN_SWITCH(N, L_R2C)
 #undef L_R2C
@@ -686,20 +729,16 @@ hipError_t launch_rows_r2c(int N, const TI* in, int64_t in_bs, int64_t in_ld, in
 }
 
 template <typename T>
-hipError_t launch_rows_c2r(int N, const cT<T>* in, int64_t in_bs, int64_t in_ld, int nrows,
-                           int nbatch, T* out, int64_t out_bs, int64_t out_ld, int nvx_out,
-                           const cT<T>* tw, hipStream_t s)
+hipError_t launch_rows_c2r(int N, const RowJobs& jobs, const cT<T>* tw, hipStream_t s)
 {
+    if (jobs.total <= 0) return hipSuccess;
 #define L_C2R(NN)                                                                          \
     {                                                                                      \
         using C = RowCfg<T, NN>;                                                           \
-        const int bpb = (nrows + C::RT - 1) / C::RT;                                       \
-        const int total = bpb * nbatch;                                                    \
         static int resident = 0;                                                           \
         if (!resident) resident = resident_blocks((const void*)k_rows_c2r<T, NN>, C::THREADS); \
-        const int grid = std::min(total, resident);                                        \
-        hipLaunchKernelGGL((k_rows_c2r<T, NN>), dim3(grid), dim3(C::THREADS), 0, s,        \
-                           in, in_bs, in_ld, nrows, out, out_bs, out_ld, nvx_out, tw, bpb, total); \
+        hipLaunchKernelGGL((k_rows_c2r<T, NN>), dim3(std::min(jobs.total, resident)),      \
+                           dim3(C::THREADS), 0, s, jobs, tw);                              \
     }
     BTTB_LEN_SWITCH(N, L_C2R)
 #undef L_C2R
@@ -723,69 +762,43 @@ hipError_t launch_cols_spec(int N, const double2* in, int ncols, int nl, cT<T>* 
 }
 
 template <typename T, int ACC>
-hipError_t launch_cols_fwd(int N, const cT<T>* X, int64_t ldx, int ny, int nz, int ncols,
-                           const cT<T>* spec, cT<T>* Y, int64_t ldy, int sy, int nrhs,
-                           const cT<T>* tw, hipStream_t s)
+hipError_t launch_cols_fwd(int N, const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
 {
-    const int NR = 1;
+    if (jobs.total <= 0) return hipSuccess;
 #define L_FWD(NN)                                                                          \
-    {                                                                                      \
-        using C = ColCfg<NN>;                                                              \
-        dim3 grid((ncols + C::CPW - 1) / C::CPW, (nrhs + NR - 1) / NR);                    \
-        hipLaunchKernelGGL((k_cols_fwd_mac<T, NN, 1, ACC>), grid, dim3(C::THREADS), 0, s, X, ldx, \
-                           ny, nz, ncols, spec, Y, ldy, sy, nrhs, tw);                     \
-    }
+    hipLaunchKernelGGL((k_cols_fwd_mac<T, NN, 1, ACC>), dim3(jobs.total), dim3(ColCfg<NN>::THREADS), 0, s, \
+                       jobs, tw);
     BTTB_LEN_SWITCH(N, L_FWD)
 #undef L_FWD
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_cols_tr(int N, const cT<T>* R, int64_t ldr, int sy, int r0, int nl, int ncols,
-                          const cT<T>* spec, cT<T>* Z, int64_t ldz, int ny, int nrhs,
-                          const cT<T>* tw, hipStream_t s)
+hipError_t launch_cols_tr(int N, const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
 {
-    const int NR = 1;
+    if (jobs.total <= 0) return hipSuccess;
 #define L_TR(NN)                                                                           \
-    {                                                                                      \
-        using C = ColCfg<NN>;                                                              \
-        dim3 grid((ncols + C::CPW - 1) / C::CPW, (nrhs + NR - 1) / NR);                    \
-        hipLaunchKernelGGL((k_cols_tr_mac<T, NN, 1>), grid, dim3(C::THREADS), 0, s, R, ldr, sy, \
-                           r0, nl, ncols, spec, Z, ldz, ny, nrhs, tw);                     \
-    }
+    hipLaunchKernelGGL((k_cols_tr_mac<T, NN, 1>), dim3(jobs.total), dim3(ColCfg<NN>::THREADS), 0, s, \
+                       jobs, tw);
     BTTB_LEN_SWITCH(N, L_TR)
 #undef L_TR
     return hipGetLastError();
 }
 
 // explicit instantiations used by the host code
-template hipError_t launch_rows_r2c<double, double>(int, const double*, int64_t, int64_t, int, int, int,
-                                                    double2*, int64_t, int64_t, const double2*, hipStream_t);
-template hipError_t launch_rows_r2c<float, float>(int, const float*, int64_t, int64_t, int, int, int,
-                                                  float2*, int64_t, int64_t, const float2*, hipStream_t);
-template hipError_t launch_rows_c2r<double>(int, const double2*, int64_t, int64_t, int, int, double*,
-                                            int64_t, int64_t, int, const double2*, hipStream_t);
-template hipError_t launch_rows_c2r<float>(int, const float2*, int64_t, int64_t, int, int, float*,
-                                           int64_t, int64_t, int, const float2*, hipStream_t);
+template hipError_t launch_rows_r2c<double, double>(int, const RowJobs&, const double2*, hipStream_t);
+template hipError_t launch_rows_r2c<float, float>(int, const RowJobs&, const float2*, hipStream_t);
+template hipError_t launch_rows_c2r<double>(int, const RowJobs&, const double2*, hipStream_t);
+template hipError_t launch_rows_c2r<float>(int, const RowJobs&, const float2*, hipStream_t);
 template hipError_t launch_cols_spec<double>(int, const double2*, int, int, double2*, int, double,
                                              const double2*, hipStream_t);
 template hipError_t launch_cols_spec<float>(int, const double2*, int, int, float2*, int, double,
                                             const double2*, hipStream_t);
-template hipError_t launch_cols_fwd<double, ACC_PLAIN>(int, const double2*, int64_t, int, int, int,
-                                                       const double2*, double2*, int64_t, int, int,
-                                                       const double2*, hipStream_t);
-template hipError_t launch_cols_fwd<float, ACC_PLAIN>(int, const float2*, int64_t, int, int, int,
-                                                      const float2*, float2*, int64_t, int, int,
-                                                      const float2*, hipStream_t);
-template hipError_t launch_cols_fwd<float, ACC_TWOSUM>(int, const float2*, int64_t, int, int, int,
-                                                       const float2*, float2*, int64_t, int, int,
-                                                       const float2*, hipStream_t);
-template hipError_t launch_cols_fwd<float, ACC_WIDE>(int, const float2*, int64_t, int, int, int,
-                                                     const float2*, float2*, int64_t, int, int,
-                                                     const float2*, hipStream_t);
-template hipError_t launch_cols_tr<double>(int, const double2*, int64_t, int, int, int, int, const double2*,
-                                           double2*, int64_t, int, int, const double2*, hipStream_t);
-template hipError_t launch_cols_tr<float>(int, const float2*, int64_t, int, int, int, int, const float2*,
-                                          float2*, int64_t, int, int, const float2*, hipStream_t);
+template hipError_t launch_cols_fwd<double, ACC_PLAIN>(int, const ColJobs&, const double2*, hipStream_t);
+template hipError_t launch_cols_fwd<float, ACC_PLAIN>(int, const ColJobs&, const float2*, hipStream_t);
+template hipError_t launch_cols_fwd<float, ACC_TWOSUM>(int, const ColJobs&, const float2*, hipStream_t);
+template hipError_t launch_cols_fwd<float, ACC_WIDE>(int, const ColJobs&, const float2*, hipStream_t);
+template hipError_t launch_cols_tr<double>(int, const ColJobs&, const double2*, hipStream_t);
+template hipError_t launch_cols_tr<float>(int, const ColJobs&, const float2*, hipStream_t);
 
 }  // namespace bttbk

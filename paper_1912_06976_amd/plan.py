@@ -206,3 +206,82 @@ class Plan:
 
     def debug_generator(self, layer: int) -> np.ndarray:
         return bttb_debug_generator(self.handle, layer, self.workspace(1))
+
+
+def bttb_batch_create(plans, max_nrhs: int = 1) -> int:
+    arr = (ctypes.c_void_p * len(plans))(*[p.handle if isinstance(p, Plan) else p for p in plans])
+    h = ctypes.c_void_p()
+    check("bttb_batch_create", _lib.load().bttb_batch_create(arr, len(plans), max_nrhs, ctypes.byref(h)))
+    return h.value
+
+
+def bttb_batch_query(batch: int) -> int:
+    wb = ctypes.c_size_t()
+    check("bttb_batch_query", _lib.load().bttb_batch_query(ctypes.c_void_p(batch), ctypes.byref(wb)))
+    return wb.value
+
+
+def bttb_batch_run(batch: int, io, workspace: torch.Tensor, stream=None) -> None:
+    arr = (_lib.BatchIO * len(io))(*io)
+    check("bttb_batch_run", _lib.load().bttb_batch_run(ctypes.c_void_p(batch), arr, _ptr(workspace),
+                                                       workspace.numel() * workspace.element_size(),
+                                                       _stream_ptr(stream)))
+
+
+def bttb_batch_destroy(batch: int) -> None:
+    check("bttb_batch_destroy", _lib.load().bttb_batch_destroy(ctypes.c_void_p(batch)))
+
+
+class Batch:
+    """Many generated plans of one precision run together as one graph launch.
+
+    ``run(ms=..., rs=...)`` takes, per plan, a model tensor (or None) for the
+    forward product and a data tensor (or None) for the transpose product and
+    returns the lists of outputs.  The plans must stay alive.
+    """
+
+    def __init__(self, plans, max_nrhs: int = 1):
+        self.plans = list(plans)
+        for p in self.plans:
+            if p.spectra is None:
+                raise RuntimeError("generate() every plan before batching it")
+        self.max_nrhs = max_nrhs
+        self.handle = bttb_batch_create(self.plans, max_nrhs)
+        self.workspace = torch.empty(bttb_batch_query(self.handle), dtype=torch.uint8,
+                                     device=self.plans[0].device)
+        self._outs = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                bttb_batch_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def run(self, ms=None, rs=None, stream=None):
+        n = len(self.plans)
+        ms = list(ms) if ms is not None else [None] * n
+        rs = list(rs) if rs is not None else [None] * n
+        io, ds, mts = [], [], []
+        for p, m, r in zip(self.plans, ms, rs):
+            nr = 1
+            d = mt = None
+            if m is not None:
+                nr = p._check_vec(m, (p.nz, p.ny, p.nx), "m")
+                d = torch.empty(m.shape[:-3] + (p.sy, p.sx), dtype=p.dtype, device=m.device)
+            if r is not None:
+                nr2 = p._check_vec(r, (p.sy, p.sx), "r")
+                if m is not None and nr2 != nr:
+                    raise ValueError("m and r of one problem need the same number of right-hand sides")
+                nr = nr2
+                mt = torch.empty(r.shape[:-2] + (p.nz, p.ny, p.nx), dtype=p.dtype, device=r.device)
+            io.append(_lib.BatchIO(p.spectra.data_ptr(), m.data_ptr() if m is not None else None,
+                                   d.data_ptr() if d is not None else None,
+                                   r.data_ptr() if r is not None else None,
+                                   mt.data_ptr() if mt is not None else None, nr))
+            ds.append(d)
+            mts.append(mt)
+        bttb_batch_run(self.handle, io, self.workspace, stream)
+        return ds, mts

@@ -1,0 +1,87 @@
+"""Batched runs (one graph launch for many uneven problems) against the
+single-problem calls and the oracle."""
+import numpy as np
+import pytest
+
+import workloads as W
+from _common import oracle_problem, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _inputs(torch, plans, nrhs, seed):
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    ms = [torch.randn((nrhs, p.nz, p.ny, p.nx), generator=g, device="cuda", dtype=p.dtype) for p in plans]
+    rs = [torch.randn((nrhs, p.sy, p.sx), generator=g, device="cuda", dtype=p.dtype) for p in plans]
+    return ms, rs
+
+
+def test_batch48_equals_single_calls_and_replays(torch_cuda):
+    torch = torch_cuda
+    from paper_1912_06976_amd import Batch, Plan
+    probs = W.batch48()
+    print("batch48 Nx/Ny pairs:", sorted({(Plan(p).nx_fft, Plan(p).ny_fft) for p in probs}), flush=True)
+    plans = [Plan(p, "fp32").generate() for p in probs]
+    ms, rs = _inputs(torch, plans, 4, 401)
+    batch = Batch(plans, max_nrhs=4)
+    ref_d = [p.forward(m) for p, m in zip(plans, ms)]
+    ref_t = [p.transpose(r) for p, r in zip(plans, rs)]
+    torch.cuda.synchronize()
+    for rep in range(3):
+        ds, mts = batch.run(ms, rs)
+        torch.cuda.synchronize()
+        for k in range(len(plans)):
+            assert torch.equal(ds[k], ref_d[k]), (rep, k)
+            assert torch.equal(mts[k], ref_t[k]), (rep, k)
+        # eager work between replays
+        extra = plans[rep].forward(ms[rep])
+        torch.cuda.synchronize()
+        assert torch.equal(extra, ref_d[rep])
+
+
+def test_batch_partial_products_and_rhs_counts(torch_cuda):
+    torch = torch_cuda
+    from paper_1912_06976_amd import Batch, Plan
+    probs = [W.magnetic_24(), W.small_gravity(), W.problem(W.MAGNETIC, 13, 11, 5, 0, 3, 4, 1, dx=25.0, dy=40.0,
+                                                         z_edges=[0, 10, 25, 45, 70, 100], h=12.5, incl=35.0,
+                                                         decl=70.0, field_nT=45000.0)]
+    probs[2]["layer_chunk"] = 2
+    plans = [Plan(p, "fp64").generate() for p in probs]
+    ms, rs = _inputs(torch, plans, 3, 7)
+    ms = [ms[0][:1], None, ms[2]]
+    rs = [None, rs[1][:2], rs[2]]
+    batch = Batch(plans, max_nrhs=3)
+    ds, mts = batch.run(ms, rs)
+    torch.cuda.synchronize()
+    assert mts[0] is None and ds[1] is None
+    assert torch.equal(ds[0], plans[0].forward(ms[0]))
+    assert torch.equal(mts[1], plans[1].transpose(rs[1]))
+    assert torch.equal(ds[2], plans[2].forward(ms[2]))
+    assert torch.equal(mts[2], plans[2].transpose(rs[2]))
+    # against the oracle's dense matrices
+    import oracle
+    G0 = oracle.dense_G_quad(oracle_problem(probs[0]))
+    assert rel_l2(ds[0].cpu().numpy().reshape(1, -1), ms[0].cpu().numpy().reshape(1, -1) @ G0.T) <= 1e-12
+    G2 = oracle.dense_G_quad(oracle_problem(probs[2]))
+    assert rel_l2(mts[2].cpu().numpy().reshape(3, -1), rs[2].cpu().numpy().reshape(3, -1) @ G2) <= 1e-12
+
+
+def test_batch_rejects_mixed_precision_and_bad_io(torch_cuda):
+    torch = torch_cuda
+    from paper_1912_06976_amd import Batch, BttbError, Plan
+    a = Plan(W.magnetic_24(), "fp32").generate()
+    b = Plan(W.small_gravity(), "fp64").generate()
+    with pytest.raises(BttbError):
+        Batch([a, b])
+    batch = Batch([a], max_nrhs=1)
+    with pytest.raises(ValueError):
+        batch.run([torch.zeros((2, 2), device="cuda")], None)
