@@ -114,8 +114,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-stations", type=int, default=6)
     ap.add_argument("--cpu-prisms", type=int, default=48)
-    ap.add_argument("--layer-chunk", type=int, default=0,
-                    help="layers per transpose pass (descriptor field layer_chunk; 0 = all)")
+    ap.add_argument("--layer-chunk", type=int, default=-1,
+                    help="layers per transpose pass (descriptor field layer_chunk; 0 = all); "
+                         "default: the autotuner's choice")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library's default kernel configuration instead of the autotuner's")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes 3 times (calibrates the "
                          "HBM byte counters of a profiler against a kernel of known traffic)")
@@ -142,7 +145,13 @@ def main():
         return
 
     pr = W.gravity_1024()
-    pr["layer_chunk"] = args.layer_chunk
+    tuned = None
+    if not args.no_autotune:
+        pr, tune_ms = B.bttb_autotune(pr, "fp32", nrhs=1)
+        tuned = {k: pr[k] for k in ("layer_chunk", "row_tile", "col_tile")}
+        log("autotuned:", tuned, "%.3f ms" % tune_ms)
+    if args.layer_chunk >= 0:
+        pr["layer_chunk"] = args.layer_chunk
     nx, ny, nz = W.dims(pr)
     cells = nx * ny * nz
     log("inputs: ellipsoid model and N(0,1) data, seeds 301 / 302")
@@ -170,7 +179,7 @@ def main():
         "config": {"workload": "gravity g_z 1000x1000 stations, 12-cell padding -> 1024x1024x128 prisms "
                                "of 25x25x20 m, 20 random ellipsoids; one G*m + one G^T*r",
                    "fft": "%dx%d" % (Nx, Ny), "nrhs": 1, "precision": "fp32 spectra/FFT/MAC, fp64 generator",
-                   "accumulation": "fp64 depth accumulator"},
+                   "accumulation": "fp64 depth accumulator", "kernel_config": tuned or "default"},
         "roofline": roof,
         "step_algorithmic_GBps": round(pb / (ms * 1e-3) / 1e9, 1),
         "step_algorithmic_bytes": pb,

@@ -106,6 +106,10 @@ typedef struct {
                                   layers); smaller chunks keep the per-layer intermediate
                                   in the device's last-level cache and shrink the
                                   workspace.  Results do not depend on it.              */
+    int32_t row_tile;          /* tuning: 0 (default) or 2 / 4 pairs of rows per block of
+                                  the row transforms                                  */
+    int32_t col_tile;          /* tuning: 0 (default) or 1 / 2 times the default number of
+                                  columns per block of the column transforms          */
 } bttb_problem_desc;
 
 typedef struct bttb_plan_s* bttb_plan_t;
@@ -189,6 +193,22 @@ bttb_status bttb_batch_run(bttb_batch_t batch, const bttb_batch_io* io, void* wo
 
 /* Release the graph, the capture stream and the batch (NULL accepted). */
 bttb_status bttb_batch_destroy(bttb_batch_t batch);
+
+/* ------------------------------------------------------------------------
+ * Autotuner (the analogue of FFTW's planner "wisdom" the paper's MATLAB
+ * runs preload, Sec. 5): for one descriptor and right-hand-side count, time
+ * the products on the device for every candidate kernel configuration
+ * (row_tile in {2, 4}, col_tile in {1, 2}, layer_chunk in {0, 8, 16, 32}
+ * below nz) and return the descriptor with the fastest one filled in.
+ * Results are cached in a text file (path: environment variable
+ * BTTB_TUNE_CACHE, default $HOME/.cache/bttb_autotune.txt), keyed by the
+ * shape, precision, accumulation, nrhs and device; a cached key is returned
+ * without timing.  Synchronises the stream.  scratch: device memory of at
+ * least bttb_autotune_query bytes (spectra, workspace and test vectors).
+ * ------------------------------------------------------------------------ */
+bttb_status bttb_autotune_query(const bttb_problem_desc* desc, int32_t nrhs, size_t* scratch_bytes);
+bttb_status bttb_autotune(const bttb_problem_desc* desc, int32_t nrhs, void* scratch, size_t scratch_bytes,
+                          void* stream, bttb_problem_desc* tuned, float* best_ms);
 
 /* Profiling hooks: the same work as bttb_forward / bttb_transpose, with HIP
  * events recorded on the stream around each of the three kernels (row

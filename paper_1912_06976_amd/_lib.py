@@ -20,7 +20,8 @@ BTTB_ACC_DEFAULT, BTTB_ACC_PLAIN, BTTB_ACC_TWOSUM, BTTB_ACC_WIDE = 0, 1, 2, 3
 EXPORTS = ["bttb_plan_create", "bttb_plan_destroy", "bttb_plan_query", "bttb_kernel_generate",
            "bttb_forward", "bttb_transpose", "bttb_forward_profiled", "bttb_transpose_profiled",
            "bttb_debug_generator", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
-           "bttb_batch_destroy", "bttb_status_string", "bttb_last_error"]
+           "bttb_batch_destroy", "bttb_autotune_query", "bttb_autotune", "bttb_status_string",
+           "bttb_last_error"]
 
 
 class BatchIO(ctypes.Structure):
@@ -41,6 +42,7 @@ class ProblemDesc(ctypes.Structure):
         ("field_nT", ctypes.c_double), ("scale", ctypes.c_double),
         ("nx_fft", ctypes.c_int32), ("ny_fft", ctypes.c_int32),
         ("accumulation", ctypes.c_int32), ("layer_chunk", ctypes.c_int32),
+        ("row_tile", ctypes.c_int32), ("col_tile", ctypes.c_int32),
     ]
 
 
@@ -77,6 +79,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
     L.bttb_batch_query.argtypes = [vp, ctypes.POINTER(sz)]
     L.bttb_batch_run.argtypes = [vp, ctypes.POINTER(BatchIO), vp, sz, vp]
     L.bttb_batch_destroy.argtypes = [vp]
+    L.bttb_autotune_query.argtypes = [ctypes.POINTER(ProblemDesc), i32, ctypes.POINTER(sz)]
+    L.bttb_autotune.argtypes = [ctypes.POINTER(ProblemDesc), i32, vp, sz, vp, ctypes.POINTER(ProblemDesc),
+                                ctypes.POINTER(ctypes.c_float)]
     L.bttb_status_string.argtypes = [ctypes.c_int]
     L.bttb_status_string.restype = ctypes.c_char_p
     L.bttb_last_error.argtypes = []
@@ -84,7 +89,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     for name in ["bttb_plan_create", "bttb_plan_destroy", "bttb_plan_query", "bttb_kernel_generate",
                  "bttb_forward", "bttb_transpose", "bttb_forward_profiled", "bttb_transpose_profiled",
                  "bttb_debug_generator", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
-                 "bttb_batch_destroy"]:
+                 "bttb_batch_destroy", "bttb_autotune_query", "bttb_autotune"]:
         getattr(L, name).restype = ctypes.c_int
     _handle = L
     return L

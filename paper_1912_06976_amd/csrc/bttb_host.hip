@@ -6,9 +6,14 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
 #include <string>
+#include <sys/stat.h>
 #include <vector>
 
 #include "../../include/bttb.h"
@@ -54,6 +59,7 @@ struct bttb_plan_s {
     // generation batch; layers per transpose pass
     int gen_batch;
     int tr_chunk;
+    int row_tile, col_tile;      // kernel tile choices (see bttb_problem_desc)
 };
 
 namespace {
@@ -101,6 +107,10 @@ bttb_status validate_and_fill(const bttb_problem_desc* d, bttb_plan_s* P)
     if (d->accumulation < BTTB_ACC_DEFAULT || d->accumulation > BTTB_ACC_WIDE)
         return fail(BTTB_ERR_INVALID_VALUE, "accumulation must be a bttb_accumulation value");
     if (d->layer_chunk < 0) return fail(BTTB_ERR_INVALID_VALUE, "layer_chunk must be >= 0");
+    if (d->row_tile != 0 && d->row_tile != 2 && d->row_tile != 4)
+        return fail(BTTB_ERR_INVALID_VALUE, "row_tile must be 0, 2 or 4");
+    if (d->col_tile != 0 && d->col_tile != 1 && d->col_tile != 2)
+        return fail(BTTB_ERR_INVALID_VALUE, "col_tile must be 0, 1 or 2");
 
     const int64_t minx = std::max<int64_t>(8, d->sx + nx - 1), miny = std::max<int64_t>(8, d->sy + ny - 1);
     int64_t Nx = d->nx_fft, Ny = d->ny_fft;
@@ -159,6 +169,8 @@ bttb_status validate_and_fill(const bttb_problem_desc* d, bttb_plan_s* P)
     P->spec_bytes = off;
     P->gen_batch = std::min(P->nz, MAX_GEN_BATCH);
     P->tr_chunk = d->layer_chunk > 0 ? std::min(d->layer_chunk, P->nz) : P->nz;
+    P->row_tile = d->row_tile ? d->row_tile : 4;
+    P->col_tile = d->col_tile ? d->col_tile : 1;
     return BTTB_OK;
 }
 
@@ -231,9 +243,10 @@ bttb_status run_generate(const bttb_plan_s* P, char* spec, char* ws, hipStream_t
         rj.njobs = 1;
         rj.j[0] = RowJob{g64, w64, (int64_t)P->Nx * P->Ny, P->Nx, (int64_t)P->ncols * P->Ny, P->Ny,
                          P->Nx, P->Ny, 0, 0};
-        rj.j[0].bpb = (P->Ny + row_group_rows<double>(P->Nx) - 1) / row_group_rows<double>(P->Nx);
+        const int rt = row_group_rows<double>(P->Nx, 4);
+        rj.j[0].bpb = (P->Ny + rt - 1) / rt;
         rj.total = rj.j[0].bpb * nl;
-        if ((st = hip_check(launch_rows_r2c<double, double>(P->Nx, rj, tw64x, s), "generator rows")) != BTTB_OK)
+        if ((st = hip_check(launch_rows_r2c<double, double>(P->Nx, 4, rj, tw64x, s), "generator rows")) != BTTB_OK)
             return st;
         if ((st = hip_check(launch_cols_spec<T>(P->Ny, w64, P->ncols, nl, out, r0, inv, tw64y, s),
                             "generator columns")) != BTTB_OK)
@@ -281,39 +294,44 @@ bttb_status launch_tables(const std::vector<JobT>& jobs, const std::vector<int>&
     return BTTB_OK;
 }
 
-// row jobs of one stage, grouped by transform length N (the key)
+// row jobs of one stage, grouped by (transform length N, row tile): the key
+// is N * 8 + tile
 template <typename T>
 struct RowStage {
     std::vector<int> keys;
     std::vector<std::vector<RowJob>> jobs;
     std::vector<std::vector<int>> work;
     std::vector<const cT<T>*> tw;
-    void add(int N, const cT<T>* twp, const RowJob& j, int nbatch)
+    void add(int N, int tile, const cT<T>* twp, const RowJob& j, int nbatch)
     {
+        const int key = N * 8 + tile;
         size_t g = 0;
-        while (g < keys.size() && keys[g] != N) ++g;
-        if (g == keys.size()) { keys.push_back(N); jobs.emplace_back(); work.emplace_back(); tw.push_back(twp); }
+        while (g < keys.size() && keys[g] != key) ++g;
+        if (g == keys.size()) { keys.push_back(key); jobs.emplace_back(); work.emplace_back(); tw.push_back(twp); }
         RowJob jj = j;
-        jj.bpb = (j.nrows + row_group_rows<T>(N) - 1) / row_group_rows<T>(N);
+        const int rt = row_group_rows<T>(N, tile);
+        jj.bpb = (j.nrows + rt - 1) / rt;
         jobs[g].push_back(jj);
         work[g].push_back(jj.bpb * nbatch);
     }
 };
 
+// column jobs grouped by (N, accumulation, column tile): key N * 16 + acc * 4 + tile
 template <typename T>
 struct ColStage {
-    std::vector<int> keys;   // N * 4 + acc
+    std::vector<int> keys;
     std::vector<std::vector<ColJob>> jobs;
     std::vector<std::vector<int>> work;
     std::vector<const cT<T>*> tw;
-    void add(int N, int acc, const cT<T>* twp, const ColJob& j)
+    void add(int N, int acc, int tile, const cT<T>* twp, const ColJob& j)
     {
-        const int key = N * 4 + acc;
+        const int key = N * 16 + acc * 4 + tile;
         size_t g = 0;
         while (g < keys.size() && keys[g] != key) ++g;
         if (g == keys.size()) { keys.push_back(key); jobs.emplace_back(); work.emplace_back(); tw.push_back(twp); }
         ColJob jj = j;
-        jj.nbx = (j.ncols + col_block_lines(N) - 1) / col_block_lines(N);
+        const int cb = col_block_lines<T>(N, tile);
+        jj.nbx = (j.ncols + cb - 1) / cb;
         jobs[g].push_back(jj);
         work[g].push_back(jj.nbx * j.nrhs);   // one right-hand side per block
     }
@@ -323,10 +341,10 @@ template <typename TI, typename T>
 bttb_status run_rows_r2c(const RowStage<T>& st, hipStream_t s)
 {
     for (size_t g = 0; g < st.keys.size(); ++g) {
-        const int N = st.keys[g];
+        const int N = st.keys[g] / 8, tile = st.keys[g] % 8;
         const cT<T>* tw = st.tw[g];
         bttb_status r = launch_tables<RowJob, RowJobs>(st.jobs[g], st.work[g],
-            [&](const RowJobs& t) { return launch_rows_r2c<TI, T>(N, t, tw, s); }, "row transforms");
+            [&](const RowJobs& t) { return launch_rows_r2c<TI, T>(N, tile, t, tw, s); }, "row transforms");
         if (r != BTTB_OK) return r;
     }
     return BTTB_OK;
@@ -336,10 +354,10 @@ template <typename T>
 bttb_status run_rows_c2r(const RowStage<T>& st, hipStream_t s)
 {
     for (size_t g = 0; g < st.keys.size(); ++g) {
-        const int N = st.keys[g];
+        const int N = st.keys[g] / 8, tile = st.keys[g] % 8;
         const cT<T>* tw = st.tw[g];
         bttb_status r = launch_tables<RowJob, RowJobs>(st.jobs[g], st.work[g],
-            [&](const RowJobs& t) { return launch_rows_c2r<T>(N, t, tw, s); }, "output row transforms");
+            [&](const RowJobs& t) { return launch_rows_c2r<T>(N, tile, t, tw, s); }, "output row transforms");
         if (r != BTTB_OK) return r;
     }
     return BTTB_OK;
@@ -349,15 +367,15 @@ template <typename T>
 bttb_status run_cols(const ColStage<T>& st, bool fwd, hipStream_t s)
 {
     for (size_t g = 0; g < st.keys.size(); ++g) {
-        const int N = st.keys[g] / 4, acc = st.keys[g] % 4;
+        const int N = st.keys[g] / 16, acc = (st.keys[g] / 4) % 4, tile = st.keys[g] % 4;
         const cT<T>* tw = st.tw[g];
         bttb_status r = launch_tables<ColJob, ColJobs>(st.jobs[g], st.work[g], [&](const ColJobs& t) {
-            if (!fwd) return launch_cols_tr<T>(N, t, tw, s);
-            if constexpr (sizeof(T) == 8) return launch_cols_fwd<T, ACC_PLAIN>(N, t, tw, s);
+            if (!fwd) return launch_cols_tr<T>(N, tile, t, tw, s);
+            if constexpr (sizeof(T) == 8) return launch_cols_fwd<T, ACC_PLAIN>(N, tile, t, tw, s);
             else {
-                if (acc == ACC_PLAIN) return launch_cols_fwd<T, ACC_PLAIN>(N, t, tw, s);
-                if (acc == ACC_TWOSUM) return launch_cols_fwd<T, ACC_TWOSUM>(N, t, tw, s);
-                return launch_cols_fwd<T, ACC_WIDE>(N, t, tw, s);
+                if (acc == ACC_PLAIN) return launch_cols_fwd<T, ACC_PLAIN>(N, tile, t, tw, s);
+                if (acc == ACC_TWOSUM) return launch_cols_fwd<T, ACC_TWOSUM>(N, tile, t, tw, s);
+                return launch_cols_fwd<T, ACC_WIDE>(N, tile, t, tw, s);
             }
         }, fwd ? "forward columns" : "transpose columns");
         if (r != BTTB_OK) return r;
@@ -380,12 +398,12 @@ bttb_status run_forward(const std::vector<Item>& items, hipStream_t s, hipEvent_
         const WsLayout L = ws_layout(P, it.nrhs);
         cT<T>* X = (cT<T>*)(it.ws + L.fwd_x);
         cT<T>* Y = (cT<T>*)(it.ws + L.fwd_y);
-        r1.add(P->Nx, tw_x<T>(P, it.spec),
+        r1.add(P->Nx, P->row_tile, tw_x<T>(P, it.spec),
                RowJob{it.in, X, (int64_t)P->nx * P->ny, P->nx, (int64_t)P->ncols * P->ny, P->ny, P->nx, P->ny, 0, 0},
                it.nrhs * P->nz);
-        c2.add(P->Ny, P->acc, tw_y<T>(P, it.spec),
+        c2.add(P->Ny, P->acc, P->col_tile, tw_y<T>(P, it.spec),
                ColJob{X, it.spec + P->off_spec, Y, P->ny, P->sy, P->ny, P->sy, 0, P->nz, P->ncols, it.nrhs, 0, 0});
-        r3.add(P->Nx, tw_x<T>(P, it.spec),
+        r3.add(P->Nx, P->row_tile, tw_x<T>(P, it.spec),
                RowJob{Y, it.out, (int64_t)P->ncols * P->sy, P->sy, (int64_t)P->sx * P->sy, P->sx, P->sx, P->sy, 0, 0},
                it.nrhs);
     }
@@ -410,7 +428,7 @@ bttb_status run_transpose(const std::vector<Item>& items, hipStream_t s, hipEven
     for (const Item& it : items) {
         const bttb_plan_s* P = it.P;
         const WsLayout L = ws_layout(P, it.nrhs);
-        r1.add(P->Nx, tw_x<T>(P, it.spec),
+        r1.add(P->Nx, P->row_tile, tw_x<T>(P, it.spec),
                RowJob{it.in, it.ws + L.tr_r, (int64_t)P->sx * P->sy, P->sx, (int64_t)P->ncols * P->sy, P->sy,
                       P->sx, P->sy, 0, 0},
                it.nrhs);
@@ -431,17 +449,17 @@ bttb_status run_transpose(const std::vector<Item>& items, hipStream_t s, hipEven
             const WsLayout L = ws_layout(P, it.nrhs);
             const cT<T>* R = (const cT<T>*)(it.ws + L.tr_r);
             cT<T>* Z = (cT<T>*)(it.ws + L.tr_z);
-            c2.add(P->Ny, 0, tw_y<T>(P, it.spec),
+            c2.add(P->Ny, 0, P->col_tile, tw_y<T>(P, it.spec),
                    ColJob{R, it.spec + P->off_spec, Z, P->sy, P->ny, P->sy, P->ny, r0, nl, P->ncols, it.nrhs, 0, 0});
             T* out = (T*)it.out;
             if (nl == P->nz) {
-                r3.add(P->Nx, tw_x<T>(P, it.spec),
+                r3.add(P->Nx, P->row_tile, tw_x<T>(P, it.spec),
                        RowJob{Z, out, (int64_t)P->ncols * P->ny, P->ny, (int64_t)P->nx * P->ny, P->nx, P->nx, P->ny,
                               0, 0},
                        it.nrhs * P->nz);
             } else {
                 for (int q = 0; q < it.nrhs; ++q)
-                    r3.add(P->Nx, tw_x<T>(P, it.spec),
+                    r3.add(P->Nx, P->row_tile, tw_x<T>(P, it.spec),
                            RowJob{Z + (size_t)q * nl * P->ncols * P->ny, out + ((size_t)q * P->nz + r0) * P->nx * P->ny,
                                   (int64_t)P->ncols * P->ny, P->ny, (int64_t)P->nx * P->ny, P->nx, P->nx, P->ny, 0, 0},
                            nl);
@@ -776,6 +794,186 @@ bttb_status bttb_batch_destroy(bttb_batch_t B)
     if (B->cap) (void)hipStreamDestroy(B->cap);
     delete B;
     return BTTB_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct TuneScratch {
+    size_t spec, ws, m, d, r, mt, total;
+};
+
+TuneScratch tune_layout(const bttb_plan_s* P, int nrhs)
+{
+    TuneScratch L{};
+    const size_t n = (size_t)P->nx * P->ny * P->nz, ms = (size_t)P->sx * P->sy;
+    L.spec = 0;
+    L.ws = align_up(P->spec_bytes);
+    L.m = align_up(L.ws + ws_layout(P, nrhs).total);   // layer_chunk 0 needs the most
+    L.d = align_up(L.m + nrhs * n * P->esz);
+    L.r = align_up(L.d + nrhs * ms * P->esz);
+    L.mt = align_up(L.r + nrhs * ms * P->esz);
+    L.total = align_up(L.mt + nrhs * n * P->esz);
+    return L;
+}
+
+std::string tune_cache_path()
+{
+    if (const char* e = std::getenv("BTTB_TUNE_CACHE")) return e;
+    const char* home = std::getenv("HOME");
+    std::string dir = std::string(home ? home : "/tmp") + "/.cache";
+    mkdir(dir.c_str(), 0755);
+    return dir + "/bttb_autotune.txt";
+}
+
+std::string tune_key(const bttb_plan_s* P, int nrhs)
+{
+    int dev = 0, ncu = 0;
+    hipDeviceProp_t prop{};
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    for (char& c : arch)
+        if (c == ' ') c = '_';
+    std::ostringstream k;
+    k << "v1 " << P->d.problem << ' ' << P->d.precision << ' ' << P->sx << ' ' << P->sy << ' ' << P->nz << ' '
+      << P->d.pxl << ' ' << P->d.pxr << ' ' << P->d.pyl << ' ' << P->d.pyr << ' ' << P->Nx << ' ' << P->Ny << ' '
+      << P->acc << ' ' << nrhs << ' ' << arch << ' ' << ncu;
+    return k.str();
+}
+
+bool tune_lookup(const std::string& key, int v[3], float* ms)
+{
+    std::ifstream f(tune_cache_path());
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t bar = line.find('|');
+        if (bar == std::string::npos || line.substr(0, bar) != key) continue;
+        std::istringstream is(line.substr(bar + 1));
+        if (is >> v[0] >> v[1] >> v[2] >> *ms) return true;
+    }
+    return false;
+}
+
+void tune_store(const std::string& key, const int v[3], float ms)
+{
+    std::ofstream f(tune_cache_path(), std::ios::app);
+    if (f) f << key << '|' << v[0] << ' ' << v[1] << ' ' << v[2] << ' ' << ms << '\n';
+}
+
+}  // namespace
+
+extern "C" {
+
+bttb_status bttb_autotune_query(const bttb_problem_desc* desc, int32_t nrhs, size_t* scratch_bytes)
+{
+    try {
+        g_last_error.clear();
+        if (!desc || !scratch_bytes) return fail(BTTB_ERR_NULL_POINTER, "desc and scratch_bytes must not be NULL");
+        if (nrhs < 1) return fail(BTTB_ERR_INVALID_VALUE, "nrhs must be >= 1");
+        bttb_plan_s P;
+        bttb_problem_desc d = *desc;
+        d.layer_chunk = 0;
+        bttb_status st = validate_and_fill(&d, &P);
+        if (st != BTTB_OK) return st;
+        *scratch_bytes = tune_layout(&P, nrhs).total;
+        return BTTB_OK;
+    } catch (...) {
+        return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_autotune_query");
+    }
+}
+
+bttb_status bttb_autotune(const bttb_problem_desc* desc, int32_t nrhs, void* scratch, size_t scratch_bytes,
+                          void* stream, bttb_problem_desc* tuned, float* best_ms)
+{
+    try {
+        g_last_error.clear();
+        if (!desc || !scratch || !tuned) return fail(BTTB_ERR_NULL_POINTER, "desc, scratch and tuned must not be NULL");
+        if (nrhs < 1) return fail(BTTB_ERR_INVALID_VALUE, "nrhs must be >= 1");
+        if (!aligned(scratch, kAlign)) return fail(BTTB_ERR_INVALID_VALUE, "scratch must be 256-byte aligned");
+        bttb_plan_s base;
+        bttb_problem_desc d0 = *desc;
+        d0.layer_chunk = 0;
+        d0.row_tile = 0;
+        d0.col_tile = 0;
+        bttb_status st = validate_and_fill(&d0, &base);
+        if (st != BTTB_OK) return st;
+        const TuneScratch L = tune_layout(&base, nrhs);
+        if (scratch_bytes < L.total) return fail(BTTB_ERR_WORKSPACE_TOO_SMALL, "scratch smaller than bttb_autotune_query reports");
+        *tuned = *desc;
+        const std::string key = tune_key(&base, nrhs);
+        int best[3];
+        float bms = 0.f;
+        if (tune_lookup(key, best, &bms)) {
+            tuned->layer_chunk = best[0];
+            tuned->row_tile = best[1];
+            tuned->col_tile = best[2];
+            if (best_ms) *best_ms = bms;
+            return BTTB_OK;
+        }
+        hipStream_t s = (hipStream_t)stream;
+        char* base_ptr = (char*)scratch;
+        char* spec = base_ptr + L.spec;
+        char* ws = base_ptr + L.ws;
+        // spectra do not depend on the tuning choices: generate once
+        st = base.fp64 ? run_generate<double>(&base, spec, ws, s) : run_generate<float>(&base, spec, ws, s);
+        if (st != BTTB_OK) return st;
+        if ((st = hip_check(hipMemsetAsync(base_ptr + L.m, 0, L.d - L.m, s), "memset")) != BTTB_OK) return st;
+        if ((st = hip_check(hipMemsetAsync(base_ptr + L.r, 0, L.mt - L.r, s), "memset")) != BTTB_OK) return st;
+        std::vector<int> chunks{0};
+        for (int c : {8, 16, 32})
+            if (c < base.nz) chunks.push_back(c);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if ((st = hip_check(hipEventCreate(&e0), "event")) != BTTB_OK) return st;
+        if ((st = hip_check(hipEventCreate(&e1), "event")) != BTTB_OK) { (void)hipEventDestroy(e0); return st; }
+        float best_t = -1.f;
+        for (int rt : {4, 2})
+            for (int ct : {1, 2})
+                for (int ch : chunks) {
+                    if (st != BTTB_OK) break;
+                    bttb_plan_s P;
+                    bttb_problem_desc d = d0;
+                    d.layer_chunk = ch;
+                    d.row_tile = rt;
+                    d.col_tile = ct;
+                    if ((st = validate_and_fill(&d, &P)) != BTTB_OK) break;
+                    auto once = [&]() -> bttb_status {
+                        bttb_status r = P.fp64 ? run_single<double>(true, &P, spec, base_ptr + L.m, base_ptr + L.d, nrhs, ws, s)
+                                               : run_single<float>(true, &P, spec, base_ptr + L.m, base_ptr + L.d, nrhs, ws, s);
+                        if (r != BTTB_OK) return r;
+                        return P.fp64 ? run_single<double>(false, &P, spec, base_ptr + L.r, base_ptr + L.mt, nrhs, ws, s)
+                                      : run_single<float>(false, &P, spec, base_ptr + L.r, base_ptr + L.mt, nrhs, ws, s);
+                    };
+                    if ((st = once()) != BTTB_OK) break;
+                    if ((st = hip_check(hipEventRecord(e0, s), "event record")) != BTTB_OK) break;
+                    for (int rep = 0; rep < 3 && st == BTTB_OK; ++rep) st = once();
+                    if (st != BTTB_OK) break;
+                    if ((st = hip_check(hipEventRecord(e1, s), "event record")) != BTTB_OK) break;
+                    if ((st = hip_check(hipEventSynchronize(e1), "event synchronize")) != BTTB_OK) break;
+                    float t = 0.f;
+                    if ((st = hip_check(hipEventElapsedTime(&t, e0, e1), "elapsed")) != BTTB_OK) break;
+                    t /= 3.f;
+                    if (best_t < 0.f || t < best_t) {
+                        best_t = t;
+                        best[0] = ch;
+                        best[1] = rt;
+                        best[2] = ct;
+                    }
+                }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (st != BTTB_OK) return st;
+        tuned->layer_chunk = best[0];
+        tuned->row_tile = best[1];
+        tuned->col_tile = best[2];
+        if (best_ms) *best_ms = best_t;
+        tune_store(key, best, best_t);
+        return BTTB_OK;
+    } catch (...) {
+        return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_autotune");
+    }
 }
 
 const char* bttb_status_string(bttb_status s)

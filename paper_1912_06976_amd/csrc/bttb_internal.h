@@ -66,19 +66,20 @@ template <typename T> using cT = typename cplx<T>::type;
 
 hipError_t launch_twiddles(double2* t64, float2* t32, int n, hipStream_t s);
 hipError_t launch_generate(const GenParams& P, int r0, int nl, double* out, hipStream_t s);
-// rows per row group and columns per column block of the kernels for length N
-template <typename T> int row_group_rows(int N);
-int col_block_lines(int N);
+// rows per row group (row tile 2 or 4 pairs) and columns per column block
+// (column tile 1 or 2 times the default) of the kernels for length N
+template <typename T> int row_group_rows(int N, int tile);
+template <typename T> int col_block_lines(int N, int tile);
 template <typename TI, typename T>
-hipError_t launch_rows_r2c(int N, const RowJobs& jobs, const cT<T>* tw, hipStream_t s);
+hipError_t launch_rows_r2c(int N, int tile, const RowJobs& jobs, const cT<T>* tw, hipStream_t s);
 template <typename T>
-hipError_t launch_rows_c2r(int N, const RowJobs& jobs, const cT<T>* tw, hipStream_t s);
+hipError_t launch_rows_c2r(int N, int tile, const RowJobs& jobs, const cT<T>* tw, hipStream_t s);
 template <typename T>
 hipError_t launch_cols_spec(int N, const double2* in, int ncols, int nl, cT<T>* spec, int r0,
                             double scale, const double2* tw, hipStream_t s);
 template <typename T, int ACC>
-hipError_t launch_cols_fwd(int N, const ColJobs& jobs, const cT<T>* tw, hipStream_t s);
+hipError_t launch_cols_fwd(int N, int tile, const ColJobs& jobs, const cT<T>* tw, hipStream_t s);
 template <typename T>
-hipError_t launch_cols_tr(int N, const ColJobs& jobs, const cT<T>* tw, hipStream_t s);
+hipError_t launch_cols_tr(int N, int tile, const ColJobs& jobs, const cT<T>* tw, hipStream_t s);
 
 }  // namespace bttbk

@@ -145,12 +145,9 @@ __device__ __forceinline__ int xcd_order(int b, int G)
 // ---------------------------------------------------------------------------
 // row transforms
 // ---------------------------------------------------------------------------
-#ifndef BTTB_ROW_PAIRS
-#define BTTB_ROW_PAIRS 4
-#endif
-template <typename T, int N> struct RowCfg {
+// P0: pairs of rows per block for long rows (a tuning choice, 2 or 4)
+template <typename T, int N, int P0 = 4> struct RowCfg {
     static constexpr int TPL = N / 8;
-    static constexpr int P0 = BTTB_ROW_PAIRS;       // pairs of rows per block for long rows
     static constexpr int PAIRS = sizeof(T) == 4 ? (N <= 2048 ? (256 / TPL > P0 ? 256 / TPL : P0) : 2)
                                                 : (N <= 1024 ? (256 / TPL > P0 ? 256 / TPL : P0)
                                                              : (N == 2048 ? 2 : 1));
@@ -184,11 +181,11 @@ template <typename JT> __device__ __forceinline__ int find_job(const JT& js, int
 // Job input: batch b, row y, column x at in[b * in_bs + y * in_ld + x],
 // x < nv valid (zero beyond, up to N); output: packed half spectra at
 // out[b * out_bs + kx * out_ld + y], kx < N/2, y < nrows.
-template <typename TI, typename T, int N>
-__global__ void __launch_bounds__((RowCfg<T, N>::THREADS))
+template <typename TI, typename T, int N, int P0>
+__global__ void __launch_bounds__((RowCfg<T, N, P0>::THREADS))
 k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
 {
-    using C = RowCfg<T, N>;
+    using C = RowCfg<T, N, P0>;
     constexpr int TPL = C::TPL;
     __shared__ cT<T> lds[C::LDS + TableTwiddles<T, N>::size()];
     const int G = gridDim.x, total = jobs.total;
@@ -271,11 +268,11 @@ k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
 // table.  Job input: in[b * in_bs + kx * in_ld + y], kx < N/2, y < nrows;
 // output: out[b * out_bs + y * out_ld + x] for x < nv (real, unnormalised
 // inverse transform; the 1/(Nx Ny) factor lives in the spectra).
-template <typename T, int N>
-__global__ void __launch_bounds__((RowCfg<T, N>::THREADS))
+template <typename T, int N, int P0>
+__global__ void __launch_bounds__((RowCfg<T, N, P0>::THREADS))
 k_rows_c2r(RowJobs jobs, const cT<T>* __restrict__ tw)
 {
-    using C = RowCfg<T, N>;
+    using C = RowCfg<T, N, P0>;
     constexpr int TPL = C::TPL;
     __shared__ cT<T> lds[C::LDS + TableTwiddles<T, N>::size()];
     const int G = gridDim.x, total = jobs.total;
@@ -355,9 +352,10 @@ k_rows_c2r(RowJobs jobs, const cT<T>* __restrict__ tw)
 #ifndef BTTB_COL_WAVES
 #define BTTB_COL_WAVES 2
 #endif
-template <int N> struct ColCfg {
+// CM: multiplier of the columns per block (a tuning choice, 1 or 2)
+template <int N, int CM = 1> struct ColCfg {
     static constexpr int TPL = N / 8;
-    static constexpr int CPW = TPL >= 256 ? 1 : 256 / TPL;   // columns per block
+    static constexpr int CPW = (TPL >= 256 ? 1 : 256 / TPL) * CM;   // columns per block
     static constexpr int THREADS = CPW * TPL;
 };
 
@@ -457,11 +455,11 @@ template <int N> __device__ __forceinline__ int mirror_idx(int t, int m) {
 // columns of one right-hand-side block of one job).  Job: a = X with
 // X[((q * nz + r) * ncols + kx) * lda + y], y < na = ny (packed row-pass
 // output), nl = nz layers; b = Y with Y[(q * ncols + kx) * ldb + y], y < nb = sy.
-template <typename T, int N, int NR, int ACC>
-__global__ void __launch_bounds__(ColCfg<N>::THREADS, BTTB_COL_WAVES)
+template <typename T, int N, int NR, int ACC, int CM>
+__global__ void __launch_bounds__((ColCfg<N, CM>::THREADS), BTTB_COL_WAVES)
 k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
 {
-    using C = ColCfg<N>;
+    using C = ColCfg<N, CM>;
     constexpr int TPL = C::TPL;
     constexpr int LL = lds_line_elems(N);
     __shared__ cT<T> lds[(C::CPW + 1) * LL];
@@ -563,11 +561,11 @@ k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
 // Job: a = R with R[(q * ncols + kx) * lda + y], y < na = sy (packed row-pass
 // output of the data); b = Z with Z[((q * nl + r - r0) * ncols + kx) * ldb + y],
 // y < nb = ny.
-template <typename T, int N, int NR>
-__global__ void __launch_bounds__(ColCfg<N>::THREADS, BTTB_COL_WAVES)
+template <typename T, int N, int NR, int CM>
+__global__ void __launch_bounds__((ColCfg<N, CM>::THREADS), BTTB_COL_WAVES)
 k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
 {
-    using C = ColCfg<N>;
+    using C = ColCfg<N, CM>;
     constexpr int TPL = C::TPL;
     constexpr int LL = lds_line_elems(N);
     __shared__ cT<T> lds[(C::CPW + 1) * LL];
@@ -693,9 +691,9 @@ hipError_t launch_generate(const GenParams& P, int r0, int nl, double* out, hipS
     return hipGetLastError();
 }
 
-template <typename T> int row_group_rows(int N)
+template <typename T> int row_group_rows(int N, int tile)
 {
-#define L_RT(NN) return RowCfg<T, NN>::RT;
+#define L_RT(NN) return tile == 2 ? RowCfg<T, NN, 2>::RT : RowCfg<T, NN, 4>::RT;
     switch (N) {
     case 8: L_RT(8) case 16: L_RT(16) case 32: L_RT(32) case 64: L_RT(64) case 128: L_RT(128)
     case 256: L_RT(256) case 512: L_RT(512) case 1024: L_RT(1024) case 2048: L_RT(2048)
@@ -703,46 +701,68 @@ template <typename T> int row_group_rows(int N)
     }
 #undef L_RT
 }
-template int row_group_rows<float>(int);
-template int row_group_rows<double>(int);
+template int row_group_rows<float>(int, int);
+template int row_group_rows<double>(int, int);
 
-int col_block_lines(int N)
+// a column tile of 2 is used only where its LDS fits in 160 KB
+template <typename T, int NN> constexpr bool col_tile2_fits()
 {
-    return N / 8 >= 256 ? 1 : 256 / (N / 8);
+    return (ColCfg<NN, 2>::CPW + 1) * lds_line_elems(NN) * (int)sizeof(cT<T>) <= 160 * 1024;
+}
+
+template <typename T> int col_block_lines(int N, int tile)
+{
+#define L_CB(NN) return (tile == 2 && col_tile2_fits<T, NN>()) ? ColCfg<NN, 2>::CPW : ColCfg<NN, 1>::CPW;
+    switch (N) {
+    case 8: L_CB(8) case 16: L_CB(16) case 32: L_CB(32) case 64: L_CB(64) case 128: L_CB(128)
+    case 256: L_CB(256) case 512: L_CB(512) case 1024: L_CB(1024) case 2048: L_CB(2048)
+    case 4096: L_CB(4096) default: return 1;
+    }
+#undef L_CB
+}
+template int col_block_lines<float>(int, int);
+template int col_block_lines<double>(int, int);
+
+template <typename TI, typename T, int NN, int P0>
+static hipError_t launch_r2c_n(const RowJobs& jobs, const cT<T>* tw, hipStream_t s)
+{
+    using C = RowCfg<T, NN, P0>;
+    static int resident = 0;
+    if (!resident) resident = resident_blocks((const void*)k_rows_r2c<TI, T, NN, P0>, C::THREADS);
+    hipLaunchKernelGGL((k_rows_r2c<TI, T, NN, P0>), dim3(std::min(jobs.total, resident)), dim3(C::THREADS), 0, s,
+                       jobs, tw);
+    return hipGetLastError();
+}
+
+template <typename T, int NN, int P0>
+static hipError_t launch_c2r_n(const RowJobs& jobs, const cT<T>* tw, hipStream_t s)
+{
+    using C = RowCfg<T, NN, P0>;
+    static int resident = 0;
+    if (!resident) resident = resident_blocks((const void*)k_rows_c2r<T, NN, P0>, C::THREADS);
+    hipLaunchKernelGGL((k_rows_c2r<T, NN, P0>), dim3(std::min(jobs.total, resident)), dim3(C::THREADS), 0, s,
+                       jobs, tw);
+    return hipGetLastError();
 }
 
 template <typename TI, typename T>
-hipError_t launch_rows_r2c(int N, const RowJobs& jobs, const cT<T>* tw, hipStream_t s)
+hipError_t launch_rows_r2c(int N, int tile, const RowJobs& jobs, const cT<T>* tw, hipStream_t s)
 {
     if (jobs.total <= 0) return hipSuccess;
-#define L_R2C(NN)                                                                          \
-    {                                                                                      \
-        using C = RowCfg<T, NN>;                                                           \
-        static int resident = 0;                                                           \
-        if (!resident) resident = resident_blocks((const void*)k_rows_r2c<TI, T, NN>, C::THREADS); \
-        hipLaunchKernelGGL((k_rows_r2c<TI, T, NN>), dim3(std::min(jobs.total, resident)),  \
-                           dim3(C::THREADS), 0, s, jobs, tw);                              \
-    }
+#define L_R2C(NN) return tile == 2 ? launch_r2c_n<TI, T, NN, 2>(jobs, tw, s) : launch_r2c_n<TI, T, NN, 4>(jobs, tw, s);
     BTTB_LEN_SWITCH(N, L_R2C)
 #undef L_R2C
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 template <typename T>
-hipError_t launch_rows_c2r(int N, const RowJobs& jobs, const cT<T>* tw, hipStream_t s)
+hipError_t launch_rows_c2r(int N, int tile, const RowJobs& jobs, const cT<T>* tw, hipStream_t s)
 {
     if (jobs.total <= 0) return hipSuccess;
-#define L_C2R(NN)                                                                          \
-    {                                                                                      \
-        using C = RowCfg<T, NN>;                                                           \
-        static int resident = 0;                                                           \
-        if (!resident) resident = resident_blocks((const void*)k_rows_c2r<T, NN>, C::THREADS); \
-        hipLaunchKernelGGL((k_rows_c2r<T, NN>), dim3(std::min(jobs.total, resident)),      \
-                           dim3(C::THREADS), 0, s, jobs, tw);                              \
-    }
+#define L_C2R(NN) return tile == 2 ? launch_c2r_n<T, NN, 2>(jobs, tw, s) : launch_c2r_n<T, NN, 4>(jobs, tw, s);
     BTTB_LEN_SWITCH(N, L_C2R)
 #undef L_C2R
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 template <typename T>
@@ -762,23 +782,37 @@ hipError_t launch_cols_spec(int N, const double2* in, int ncols, int nl, cT<T>* 
 }
 
 template <typename T, int ACC>
-hipError_t launch_cols_fwd(int N, const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
+hipError_t launch_cols_fwd(int N, int tile, const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
 {
     if (jobs.total <= 0) return hipSuccess;
 #define L_FWD(NN)                                                                          \
-    hipLaunchKernelGGL((k_cols_fwd_mac<T, NN, 1, ACC>), dim3(jobs.total), dim3(ColCfg<NN>::THREADS), 0, s, \
-                       jobs, tw);
+    if constexpr (col_tile2_fits<T, NN>()) {                                               \
+        if (tile == 2) {                                                                   \
+            hipLaunchKernelGGL((k_cols_fwd_mac<T, NN, 1, ACC, 2>), dim3(jobs.total), dim3(ColCfg<NN, 2>::THREADS), \
+                               0, s, jobs, tw);                                            \
+            break;                                                                         \
+        }                                                                                  \
+    }                                                                                      \
+    hipLaunchKernelGGL((k_cols_fwd_mac<T, NN, 1, ACC, 1>), dim3(jobs.total), dim3(ColCfg<NN, 1>::THREADS), 0, \
+                       s, jobs, tw);
     BTTB_LEN_SWITCH(N, L_FWD)
 #undef L_FWD
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_cols_tr(int N, const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
+hipError_t launch_cols_tr(int N, int tile, const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
 {
     if (jobs.total <= 0) return hipSuccess;
 #define L_TR(NN)                                                                           \
-    hipLaunchKernelGGL((k_cols_tr_mac<T, NN, 1>), dim3(jobs.total), dim3(ColCfg<NN>::THREADS), 0, s, \
+    if constexpr (col_tile2_fits<T, NN>()) {                                               \
+        if (tile == 2) {                                                                   \
+            hipLaunchKernelGGL((k_cols_tr_mac<T, NN, 1, 2>), dim3(jobs.total), dim3(ColCfg<NN, 2>::THREADS), 0, \
+                               s, jobs, tw);                                               \
+            break;                                                                         \
+        }                                                                                  \
+    }                                                                                      \
+    hipLaunchKernelGGL((k_cols_tr_mac<T, NN, 1, 1>), dim3(jobs.total), dim3(ColCfg<NN, 1>::THREADS), 0, s, \
                        jobs, tw);
     BTTB_LEN_SWITCH(N, L_TR)
 #undef L_TR
@@ -786,19 +820,19 @@ hipError_t launch_cols_tr(int N, const ColJobs& jobs, const cT<T>* tw, hipStream
 }
 
 // explicit instantiations used by the host code
-template hipError_t launch_rows_r2c<double, double>(int, const RowJobs&, const double2*, hipStream_t);
-template hipError_t launch_rows_r2c<float, float>(int, const RowJobs&, const float2*, hipStream_t);
-template hipError_t launch_rows_c2r<double>(int, const RowJobs&, const double2*, hipStream_t);
-template hipError_t launch_rows_c2r<float>(int, const RowJobs&, const float2*, hipStream_t);
+template hipError_t launch_rows_r2c<double, double>(int, int, const RowJobs&, const double2*, hipStream_t);
+template hipError_t launch_rows_r2c<float, float>(int, int, const RowJobs&, const float2*, hipStream_t);
+template hipError_t launch_rows_c2r<double>(int, int, const RowJobs&, const double2*, hipStream_t);
+template hipError_t launch_rows_c2r<float>(int, int, const RowJobs&, const float2*, hipStream_t);
 template hipError_t launch_cols_spec<double>(int, const double2*, int, int, double2*, int, double,
                                              const double2*, hipStream_t);
 template hipError_t launch_cols_spec<float>(int, const double2*, int, int, float2*, int, double,
                                             const double2*, hipStream_t);
-template hipError_t launch_cols_fwd<double, ACC_PLAIN>(int, const ColJobs&, const double2*, hipStream_t);
-template hipError_t launch_cols_fwd<float, ACC_PLAIN>(int, const ColJobs&, const float2*, hipStream_t);
-template hipError_t launch_cols_fwd<float, ACC_TWOSUM>(int, const ColJobs&, const float2*, hipStream_t);
-template hipError_t launch_cols_fwd<float, ACC_WIDE>(int, const ColJobs&, const float2*, hipStream_t);
-template hipError_t launch_cols_tr<double>(int, const ColJobs&, const double2*, hipStream_t);
-template hipError_t launch_cols_tr<float>(int, const ColJobs&, const float2*, hipStream_t);
+template hipError_t launch_cols_fwd<double, ACC_PLAIN>(int, int, const ColJobs&, const double2*, hipStream_t);
+template hipError_t launch_cols_fwd<float, ACC_PLAIN>(int, int, const ColJobs&, const float2*, hipStream_t);
+template hipError_t launch_cols_fwd<float, ACC_TWOSUM>(int, int, const ColJobs&, const float2*, hipStream_t);
+template hipError_t launch_cols_fwd<float, ACC_WIDE>(int, int, const ColJobs&, const float2*, hipStream_t);
+template hipError_t launch_cols_tr<double>(int, int, const ColJobs&, const double2*, hipStream_t);
+template hipError_t launch_cols_tr<float>(int, int, const ColJobs&, const float2*, hipStream_t);
 
 }  // namespace bttbk

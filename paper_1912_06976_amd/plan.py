@@ -49,7 +49,8 @@ def make_desc(problem: dict, precision: str = "fp32", accumulation: str = "defau
         inclination_deg=problem.get("incl", 90.0), declination_deg=problem.get("decl", 0.0),
         field_nT=problem.get("field_nT", 50000.0), scale=problem.get("scale", 0.0),
         nx_fft=problem.get("nx_fft", 0), ny_fft=problem.get("ny_fft", 0),
-        accumulation=_ACC[accumulation], layer_chunk=problem.get("layer_chunk", 0))
+        accumulation=_ACC[accumulation], layer_chunk=problem.get("layer_chunk", 0),
+        row_tile=problem.get("row_tile", 0), col_tile=problem.get("col_tile", 0))
     return d, keep
 
 
@@ -285,3 +286,24 @@ class Batch:
             mts.append(mt)
         bttb_batch_run(self.handle, io, self.workspace, stream)
         return ds, mts
+
+
+def bttb_autotune(problem: dict, precision: str = "fp32", nrhs: int = 1, accumulation: str = "default",
+                  stream=None):
+    """Time the candidate kernel configurations for this problem on the
+    current device (or read them from the on-disk cache) and return
+    (problem dict with layer_chunk / row_tile / col_tile filled in, ms per
+    forward + transpose pair)."""
+    L = _lib.load()
+    d, keep = make_desc(problem, precision, accumulation)
+    sb = ctypes.c_size_t()
+    check("bttb_autotune_query", L.bttb_autotune_query(ctypes.byref(d), nrhs, ctypes.byref(sb)))
+    scratch = torch.empty(sb.value, dtype=torch.uint8, device="cuda")
+    out = _lib.ProblemDesc()
+    ms = ctypes.c_float()
+    check("bttb_autotune", L.bttb_autotune(ctypes.byref(d), nrhs, _ptr(scratch), sb.value, _stream_ptr(stream),
+                                           ctypes.byref(out), ctypes.byref(ms)))
+    del keep, scratch
+    tuned = dict(problem)
+    tuned.update(layer_chunk=out.layer_chunk, row_tile=out.row_tile, col_tile=out.col_tile)
+    return tuned, ms.value

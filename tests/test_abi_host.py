@@ -58,6 +58,7 @@ def _create(prob, prec="fp32", **over):
     ("sx", 0, 1), ("sy", -3, 1), ("nz", 0, 1), ("pxl", -1, 1), ("dx", 0.0, 1), ("dy", float("nan"), 1),
     ("dz", -1.0, 1), ("station_height", -1.0, 1), ("problem", 7, 1), ("precision", 3, 1),
     ("nx", 17, 1), ("nx_fft", 16, 1), ("nx_fft", 96, 3), ("ny_fft", 8192, 3), ("accumulation", 9, 1),
+    ("layer_chunk", -1, 1), ("row_tile", 3, 1), ("col_tile", 4, 1),
 ])
 def test_invalid_descriptors_rejected(lib, field, value, status):
     st, h, msg = _create(W.small_gravity(), **{field: value})
@@ -133,3 +134,17 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_handle", None)
     with pytest.raises(RuntimeError):
         _lib.load(str(tmp_path / "missing.so"))
+
+
+def test_autotune_query_size(lib):
+    from paper_1912_06976_amd.plan import make_desc
+    import paper_1912_06976_amd as B
+    d, keep = make_desc(W.gravity_1024(), "fp32")
+    sz = ctypes.c_size_t()
+    assert lib.bttb_autotune_query(ctypes.byref(d), 1, ctypes.byref(sz)) == 0
+    h = B.bttb_plan_create(W.gravity_1024(), "fp32")
+    sb, wb, _, _ = B.bttb_plan_query(h, 1)
+    B.bttb_plan_destroy(h)
+    vec = 2 * (1024 * 1024 * 128 + 1000 * 1000) * 4
+    assert sb + wb + vec <= sz.value <= sb + wb + vec + 8 * 256
+    assert lib.bttb_autotune_query(ctypes.byref(d), 0, ctypes.byref(sz)) == 1

@@ -85,3 +85,25 @@ def test_batch_rejects_mixed_precision_and_bad_io(torch_cuda):
     batch = Batch([a], max_nrhs=1)
     with pytest.raises(ValueError):
         batch.run([torch.zeros((2, 2), device="cuda")], None)
+
+
+def test_autotune_choices_preserve_results_and_cache(torch_cuda, tmp_path, monkeypatch):
+    torch = torch_cuda
+    from paper_1912_06976_amd import Plan, bttb_autotune
+    monkeypatch.setenv("BTTB_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    pr = W.problem(W.MAGNETIC, 60, 40, 20, 2, 3, 1, 4, dx=50.0, dy=50.0, dz=25.0, incl=60.0, decl=15.0,
+                   field_nT=47000.0)
+    tuned, ms = bttb_autotune(pr, "fp32", nrhs=2)
+    assert tuned["row_tile"] in (2, 4) and tuned["col_tile"] in (1, 2)
+    assert tuned["layer_chunk"] in (0, 8, 16) and ms > 0
+    lines = open(tmp_path / "tune.txt").read().splitlines()
+    assert len(lines) == 1
+    again, ms2 = bttb_autotune(pr, "fp32", nrhs=2)       # from the cache
+    assert again == tuned and abs(ms2 - ms) < 1e-3 * ms
+    assert len(open(tmp_path / "tune.txt").read().splitlines()) == 1
+    ms_, rs = _inputs(torch, [Plan(pr, "fp32")], 2, 11)
+    base = Plan(pr, "fp32").generate()
+    for cfg in ({"row_tile": 2, "col_tile": 2, "layer_chunk": 8}, {"row_tile": 4, "col_tile": 2}, tuned):
+        p = Plan(dict(pr, **cfg), "fp32").generate()
+        assert torch.equal(p.forward(ms_[0]), base.forward(ms_[0]))
+        assert torch.equal(p.transpose(rs[0]), base.transpose(rs[0]))
