@@ -323,7 +323,10 @@ struct ColStage {
     std::vector<std::vector<ColJob>> jobs;
     std::vector<std::vector<int>> work;
     std::vector<const cT<T>*> tw;
-    void add(int N, int acc, int tile, const cT<T>* twp, const ColJob& j)
+    // units: work items per (right-hand side, column block): 1 for the
+    // forward kernel (one block each), the layers for the persistent
+    // transpose kernel
+    void add(int N, int acc, int tile, const cT<T>* twp, const ColJob& j, int units = 1)
     {
         const int key = N * 16 + acc * 4 + tile;
         size_t g = 0;
@@ -333,7 +336,7 @@ struct ColStage {
         const int cb = col_block_lines<T>(N, tile);
         jj.nbx = (j.ncols + cb - 1) / cb;
         jobs[g].push_back(jj);
-        work[g].push_back(jj.nbx * j.nrhs);   // one right-hand side per block
+        work[g].push_back(jj.nbx * j.nrhs * units);
     }
 };
 
@@ -450,7 +453,8 @@ bttb_status run_transpose(const std::vector<Item>& items, hipStream_t s, hipEven
             const cT<T>* R = (const cT<T>*)(it.ws + L.tr_r);
             cT<T>* Z = (cT<T>*)(it.ws + L.tr_z);
             c2.add(P->Ny, 0, P->col_tile, tw_y<T>(P, it.spec),
-                   ColJob{R, it.spec + P->off_spec, Z, P->sy, P->ny, P->sy, P->ny, r0, nl, P->ncols, it.nrhs, 0, 0});
+                   ColJob{R, it.spec + P->off_spec, Z, P->sy, P->ny, P->sy, P->ny, r0, nl, P->ncols, it.nrhs, 0, 0},
+                   nl);
             T* out = (T*)it.out;
             if (nl == P->nz) {
                 r3.add(P->Nx, P->row_tile, tw_x<T>(P, it.spec),

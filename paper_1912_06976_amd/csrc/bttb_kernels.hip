@@ -561,6 +561,12 @@ k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
 // Job: a = R with R[(q * ncols + kx) * lda + y], y < na = sy (packed row-pass
 // output of the data); b = Z with Z[((q * nl + r - r0) * ncols + kx) * ldb + y],
 // y < nb = ny.
+// The kernel is persistent and balanced: the work of all jobs is the list of
+// units (job, right-hand side q, column block cb, layer l), layer fastest,
+// and block w processes the contiguous range [w U / G, (w + 1) U / G).  A
+// block recomputes R^ = FFT_y(R) whenever its range enters a new column
+// block (at most a few times), so every block gets the same number of layers
+// whatever the number of resident blocks.
 template <typename T, int N, int NR, int CM>
 __global__ void __launch_bounds__((ColCfg<N, CM>::THREADS), BTTB_COL_WAVES)
 k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
@@ -569,81 +575,83 @@ k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
     constexpr int TPL = C::TPL;
     constexpr int LL = lds_line_elems(N);
     __shared__ cT<T> lds[(C::CPW + 1) * LL];
-    const ColJob& J = jobs.j[find_job(jobs, blockIdx.x)];
-    const cT<T>* __restrict__ R = (const cT<T>*)J.a;
-    const cT<T>* __restrict__ spec = (const cT<T>*)J.spec;
-    cT<T>* __restrict__ Z = (cT<T>*)J.b;
-    const int64_t ldr = J.lda, ldz = J.ldb;
-    const int sy = J.na, ny = J.nb, r0 = J.r0, nl = J.nl, ncols = J.ncols, nrhs = J.nrhs;
-    const int lb = blockIdx.x - J.begin, cb = lb % J.nbx;
     const int cl = threadIdx.x / TPL, t = threadIdx.x % TPL;
-    const int col = cb * C::CPW + cl;
-    const int q0 = (lb / J.nbx) * NR;
-    const bool ok = col < ncols;
-    const bool packed_blk = cb == 0;
-    const bool packed = packed_blk && cl == 0;
     cT<T>* xl = lds + cl * LL;
     cT<T>* xs2 = lds + C::CPW * LL;
     LineTwiddles<T, N> twl;
     twl.load(tw, t);
-    const int ccol = ok ? col : 0;
-    cT<T> rh[NR][8];
-    const bool zhi = sy <= N / 2;
-#pragma unroll
-    for (int q = 0; q < NR; ++q) {
-        const int qq = q0 + q;
-        const cT<T>* rs = R + ((int64_t)(qq < nrhs ? qq : 0) * ncols + ccol) * ldr;
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const int y = t + m * TPL;
-            rh[q][m] = (ok && qq < nrhs && y < sy) ? rs[y] : mk<T>(0, 0);
-        }
-        if (zhi) fft_line<T, N, -1, true>(rh[q], xl, twl, t);
-        else fft_line<T, N, -1, false>(rh[q], xl, twl, t);
-    }
+    const int64_t U = jobs.total, G = gridDim.x;
+    const int u0 = (int)((int64_t)blockIdx.x * U / G), u1 = (int)((int64_t)(blockIdx.x + 1) * U / G);
+    // unit u -> (job k, key = q * nbx + cb, layer l)
+    auto decode = [&](int u, int& k, int& key, int& l) {
+        k = find_job(jobs, u);
+        const int lu = u - jobs.j[k].begin;
+        l = lu % jobs.j[k].nl;
+        key = lu / jobs.j[k].nl;
+    };
     cT<T> tn[8];
-    {
-        const cT<T>* sp = spec + ((int64_t)r0 * ncols + ccol) * N;
+    auto load_spec = [&](int u) {
+        int k, key, l;
+        decode(u, k, key, l);
+        const ColJob& J = jobs.j[k];
+        const int col = (key % J.nbx) * C::CPW + cl;
+        const cT<T>* sp = (const cT<T>*)J.spec + ((int64_t)(J.r0 + l) * J.ncols + (col < J.ncols ? col : 0)) * N;
 #pragma unroll
         for (int m = 0; m < 8; ++m) tn[m] = sp[t + m * TPL];
-    }
-    for (int r = r0; r < r0 + nl; ++r) {
+    };
+    int cur_k = -1, cur_key = -1;
+    cT<T> rh[8];
+    if (u0 < u1) load_spec(u0);
+    for (int u = u0; u < u1; ++u) {
+        int k, key, l;
+        decode(u, k, key, l);
+        const ColJob& J = jobs.j[k];
+        const int cb = key % J.nbx, q = key / J.nbx;
+        const int col = cb * C::CPW + cl;
+        const bool ok = col < J.ncols;
+        const bool packed_blk = cb == 0;
+        const bool packed = packed_blk && cl == 0;
         cT<T> tv[8];
 #pragma unroll
         for (int m = 0; m < 8; ++m) tv[m] = tn[m];
-        if (r + 1 < r0 + nl) {
-            const cT<T>* sp = spec + ((int64_t)(r + 1) * ncols + ccol) * N;
+        if (u + 1 < u1) load_spec(u + 1);
+        if (k != cur_k || key != cur_key) {
+            // R^ of this column: FFT_y of the packed row-pass output of the data
+            const cT<T>* rs = (const cT<T>*)J.a + ((int64_t)q * J.ncols + (ok ? col : 0)) * J.lda;
 #pragma unroll
-            for (int m = 0; m < 8; ++m) tn[m] = sp[t + m * TPL];
-        }
-#pragma unroll
-        for (int q = 0; q < NR; ++q) {
-            const int qq = q0 + q;
-            cT<T> v[8];
-#pragma unroll
-            for (int m = 0; m < 8; ++m) v[m] = cmulc<T>(rh[q][m], tv[m]);
-            if (packed_blk) {
-                stage_pair<T, N>(rh[q], tv, xl, xs2, t, packed);
-                if (packed) {
-                    // column 0: conj(T0) R0 + i conj(T1) R1
-#pragma unroll
-                    for (int m = 0; m < 8; ++m) {
-                        const int mi = mirror_idx<N>(t, m);
-                        const cT<T> rr = xl[mi], tr = xs2[mi];
-                        const cT<T> p0 = cmulc<T>(herm_a<T>(rh[q][m], rr), herm_a<T>(tv[m], tr));
-                        const cT<T> p1 = cmulc<T>(herm_b<T>(rh[q][m], rr), herm_b<T>(tv[m], tr));
-                        v[m] = mk<T>(p0.x - p1.y, p0.y + p1.x);
-                    }
-                }
+            for (int m = 0; m < 8; ++m) {
+                const int y = t + m * TPL;
+                rh[m] = (ok && y < J.na) ? rs[y] : mk<T>(0, 0);
             }
-            fft_line<T, N, +1, false>(v, xl, twl, t);
-            if (ok && qq < nrhs) {
-                cT<T>* zs = Z + (((int64_t)qq * nl + (r - r0)) * ncols + col) * ldz;
+            if (J.na <= N / 2) fft_line<T, N, -1, true>(rh, xl, twl, t);
+            else fft_line<T, N, -1, false>(rh, xl, twl, t);
+            cur_k = k;
+            cur_key = key;
+        }
+        cT<T> v[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = cmulc<T>(rh[m], tv[m]);
+        if (packed_blk) {
+            stage_pair<T, N>(rh, tv, xl, xs2, t, packed);
+            if (packed) {
+                // column 0: conj(T0) R0 + i conj(T1) R1
 #pragma unroll
                 for (int m = 0; m < 8; ++m) {
-                    const int y = t + m * TPL;
-                    if (y < ny) zs[y] = v[m];
+                    const int mi = mirror_idx<N>(t, m);
+                    const cT<T> rr = xl[mi], tr = xs2[mi];
+                    const cT<T> p0 = cmulc<T>(herm_a<T>(rh[m], rr), herm_a<T>(tv[m], tr));
+                    const cT<T> p1 = cmulc<T>(herm_b<T>(rh[m], rr), herm_b<T>(tv[m], tr));
+                    v[m] = mk<T>(p0.x - p1.y, p0.y + p1.x);
                 }
+            }
+        }
+        fft_line<T, N, +1, false>(v, xl, twl, t);
+        if (ok) {
+            cT<T>* zs = (cT<T>*)J.b + (((int64_t)q * J.nl + l) * J.ncols + col) * J.ldb;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int y = t + m * TPL;
+                if (y < J.nb) zs[y] = v[m];
             }
         }
     }
@@ -800,6 +808,16 @@ hipError_t launch_cols_fwd(int N, int tile, const ColJobs& jobs, const cT<T>* tw
     return hipGetLastError();
 }
 
+// persistent: as many blocks as are resident at once (at most one per unit)
+template <typename T, int NN, int CM>
+static void launch_tr_n(const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
+{
+    static int resident = 0;
+    if (!resident) resident = resident_blocks((const void*)k_cols_tr_mac<T, NN, 1, CM>, ColCfg<NN, CM>::THREADS);
+    hipLaunchKernelGGL((k_cols_tr_mac<T, NN, 1, CM>), dim3(std::min(jobs.total, resident)),
+                       dim3(ColCfg<NN, CM>::THREADS), 0, s, jobs, tw);
+}
+
 template <typename T>
 hipError_t launch_cols_tr(int N, int tile, const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
 {
@@ -807,13 +825,11 @@ hipError_t launch_cols_tr(int N, int tile, const ColJobs& jobs, const cT<T>* tw,
 #define L_TR(NN)                                                                           \
     if constexpr (col_tile2_fits<T, NN>()) {                                               \
         if (tile == 2) {                                                                   \
-            hipLaunchKernelGGL((k_cols_tr_mac<T, NN, 1, 2>), dim3(jobs.total), dim3(ColCfg<NN, 2>::THREADS), 0, \
-                               s, jobs, tw);                                               \
+            launch_tr_n<T, NN, 2>(jobs, tw, s);                                            \
             break;                                                                         \
         }                                                                                  \
     }                                                                                      \
-    hipLaunchKernelGGL((k_cols_tr_mac<T, NN, 1, 1>), dim3(jobs.total), dim3(ColCfg<NN, 1>::THREADS), 0, s, \
-                       jobs, tw);
+    launch_tr_n<T, NN, 1>(jobs, tw, s);
     BTTB_LEN_SWITCH(N, L_TR)
 #undef L_TR
     return hipGetLastError();
