@@ -117,6 +117,8 @@ def main():
     ap.add_argument("--layer-chunk", type=int, default=-1,
                     help="layers per transpose pass (descriptor field layer_chunk; 0 = all); "
                          "default: the autotuner's choice")
+    ap.add_argument("--row-tile", type=int, default=0, help="row kernel tile (2, 4 or 8); default: tuned")
+    ap.add_argument("--col-tile", type=int, default=0, help="column kernel tile (1 or 2); default: tuned")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's default kernel configuration instead of the autotuner's")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -152,6 +154,10 @@ def main():
         log("autotuned:", tuned, "%.3f ms" % tune_ms)
     if args.layer_chunk >= 0:
         pr["layer_chunk"] = args.layer_chunk
+    if args.row_tile:
+        pr["row_tile"] = args.row_tile
+    if args.col_tile:
+        pr["col_tile"] = args.col_tile
     nx, ny, nz = W.dims(pr)
     cells = nx * ny * nz
     log("inputs: ellipsoid model and N(0,1) data, seeds 301 / 302")

@@ -107,8 +107,8 @@ bttb_status validate_and_fill(const bttb_problem_desc* d, bttb_plan_s* P)
     if (d->accumulation < BTTB_ACC_DEFAULT || d->accumulation > BTTB_ACC_WIDE)
         return fail(BTTB_ERR_INVALID_VALUE, "accumulation must be a bttb_accumulation value");
     if (d->layer_chunk < 0) return fail(BTTB_ERR_INVALID_VALUE, "layer_chunk must be >= 0");
-    if (d->row_tile != 0 && d->row_tile != 2 && d->row_tile != 4)
-        return fail(BTTB_ERR_INVALID_VALUE, "row_tile must be 0, 2 or 4");
+    if (d->row_tile != 0 && d->row_tile != 1 && d->row_tile != 2 && d->row_tile != 4 && d->row_tile != 8)
+        return fail(BTTB_ERR_INVALID_VALUE, "row_tile must be 0, 1, 2, 4 or 8");
     if (d->col_tile != 0 && d->col_tile != 1 && d->col_tile != 2)
         return fail(BTTB_ERR_INVALID_VALUE, "col_tile must be 0, 1 or 2");
 
@@ -295,7 +295,7 @@ bttb_status launch_tables(const std::vector<JobT>& jobs, const std::vector<int>&
 }
 
 // row jobs of one stage, grouped by (transform length N, row tile): the key
-// is N * 8 + tile
+// is N * 16 + tile (tile < 16)
 template <typename T>
 struct RowStage {
     std::vector<int> keys;
@@ -304,7 +304,7 @@ struct RowStage {
     std::vector<const cT<T>*> tw;
     void add(int N, int tile, const cT<T>* twp, const RowJob& j, int nbatch)
     {
-        const int key = N * 8 + tile;
+        const int key = N * 16 + tile;
         size_t g = 0;
         while (g < keys.size() && keys[g] != key) ++g;
         if (g == keys.size()) { keys.push_back(key); jobs.emplace_back(); work.emplace_back(); tw.push_back(twp); }
@@ -344,7 +344,7 @@ template <typename TI, typename T>
 bttb_status run_rows_r2c(const RowStage<T>& st, hipStream_t s)
 {
     for (size_t g = 0; g < st.keys.size(); ++g) {
-        const int N = st.keys[g] / 8, tile = st.keys[g] % 8;
+        const int N = st.keys[g] / 16, tile = st.keys[g] % 16;
         const cT<T>* tw = st.tw[g];
         bttb_status r = launch_tables<RowJob, RowJobs>(st.jobs[g], st.work[g],
             [&](const RowJobs& t) { return launch_rows_r2c<TI, T>(N, tile, t, tw, s); }, "row transforms");
@@ -357,7 +357,7 @@ template <typename T>
 bttb_status run_rows_c2r(const RowStage<T>& st, hipStream_t s)
 {
     for (size_t g = 0; g < st.keys.size(); ++g) {
-        const int N = st.keys[g] / 8, tile = st.keys[g] % 8;
+        const int N = st.keys[g] / 16, tile = st.keys[g] % 16;
         const cT<T>* tw = st.tw[g];
         bttb_status r = launch_tables<RowJob, RowJobs>(st.jobs[g], st.work[g],
             [&](const RowJobs& t) { return launch_rows_c2r<T>(N, tile, t, tw, s); }, "output row transforms");
@@ -933,7 +933,7 @@ bttb_status bttb_autotune(const bttb_problem_desc* desc, int32_t nrhs, void* scr
         if ((st = hip_check(hipEventCreate(&e0), "event")) != BTTB_OK) return st;
         if ((st = hip_check(hipEventCreate(&e1), "event")) != BTTB_OK) { (void)hipEventDestroy(e0); return st; }
         float best_t = -1.f;
-        for (int rt : {4, 2})
+        for (int rt : {4, 2, 8})
             for (int ct : {1, 2})
                 for (int ch : chunks) {
                     if (st != BTTB_OK) break;

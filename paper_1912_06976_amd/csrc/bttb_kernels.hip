@@ -23,6 +23,8 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 
 #include "fft_core.h"
 #include "bttb_internal.h"
@@ -339,6 +341,178 @@ k_rows_c2r(RowJobs jobs, const cT<T>* __restrict__ tw)
             if (x < J.nv) {
                 if (ra < J.nrows) dst[(int64_t)ra * J.out_ld + x] = v[m].x;
                 if (rb < J.nrows) dst[(int64_t)rb * J.out_ld + x] = v[m].y;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// row transforms, tile-per-thread variant (row tile 8)
+// ---------------------------------------------------------------------------
+// A tile is 8 consecutive rows of one batch.  The TPL = N/8 threads of a
+// tile each hold, for their 8 positions x = t + m TPL, the values of all 8
+// rows; the 4 packed pairs of rows are transformed one after another through
+// one LDS line buffer, and every thread writes (r2c) or reads (c2r) the 8
+// rows of each of its half-spectrum columns as one contiguous 8-element
+// segment of the column-major layout, straight from registers.  No staging
+// tile is needed, so the LDS per block is one line buffer and the twiddle
+// table, and several independent blocks share a CU.
+template <int N> struct TileCfg {
+    static constexpr int TPL = N / 8;
+    static constexpr int LPB = TPL >= 256 ? 1 : 256 / TPL;   // tiles per block
+    static constexpr int THREADS = LPB * TPL;
+};
+
+template <typename TI, typename T, int N>
+__global__ void __launch_bounds__(TileCfg<N>::THREADS)
+k_rows_r2c_t(RowJobs jobs, const cT<T>* __restrict__ tw)
+{
+    using C = TileCfg<N>;
+    constexpr int TPL = C::TPL;
+    constexpr int LL = lds_line_elems(N);
+    __shared__ cT<T> lds[C::LPB * LL + TableTwiddles<T, N>::size()];
+    TableTwiddles<T, N>::build(lds + C::LPB * LL, tw, threadIdx.x, C::THREADS);
+    __syncthreads();
+    const TableTwiddles<T, N> twl{lds + C::LPB * LL};
+    const int tl = threadIdx.x / TPL, t = threadIdx.x % TPL;
+    cT<T>* xl = lds + tl * LL;
+    const int total = jobs.total;
+    const int nb = (total + C::LPB - 1) / C::LPB;           // block-level iterations
+    for (int gb = xcd_order(blockIdx.x, gridDim.x); gb < nb; gb += gridDim.x) {
+        const int g = gb * C::LPB + tl;
+        const bool live = g < total;
+        const RowJob& J = jobs.j[find_job(jobs, live ? g : 0)];
+        const int gl = (live ? g : 0) - J.begin;
+        const int b = gl / J.bpb, row0 = (gl % J.bpb) * 8;
+        const TI* src = (const TI*)J.in + (int64_t)b * J.in_bs;
+        T a[8][8];
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr)
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int x = t + m * TPL;
+                a[rr][m] = (live && x < J.nv && row0 + rr < J.nrows) ? (T)src[(int64_t)(row0 + rr) * J.in_ld + x] : (T)0;
+            }
+        cT<T> o[4][8];   // o[m][row]: half-spectrum value at k = t + m TPL
+        cT<T> o0n[2];    // bin N/2 of the pair's two rows (thread 0)
+        const bool zhi = J.nv <= N / 2;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            cT<T> v[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) v[m] = mk<T>(a[2 * p][m], a[2 * p + 1][m]);
+            if (zhi) fft_line<T, N, -1, true>(v, xl, twl, t);
+            else fft_line<T, N, -1, false>(v, xl, twl, t);
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < 8; ++m) xl[lpad(t + m * TPL)] = v[m];
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < 5; ++m) {
+                const int k = t + m * TPL;
+                if (m < 4 || t == 0) {
+                    const cT<T> z = v[m], zr = xl[lpad((N - k) & (N - 1))];
+                    const cT<T> A = mk<T>((T)0.5 * (z.x + zr.x), (T)0.5 * (z.y - zr.y));
+                    const cT<T> Cc = mk<T>((T)0.5 * (z.y + zr.y), (T)0.5 * (zr.x - z.x));
+                    if (m < 4) {
+                        o[m][2 * p] = A;
+                        o[m][2 * p + 1] = Cc;
+                    } else {
+                        o0n[0] = A;
+                        o0n[1] = Cc;
+                    }
+                }
+            }
+            if (t == 0) {   // pack the real bins 0 and N/2 into slot 0
+                o[0][2 * p] = mk<T>(o[0][2 * p].x, o0n[0].x);
+                o[0][2 * p + 1] = mk<T>(o[0][2 * p + 1].x, o0n[1].x);
+            }
+        }
+        if (live) {
+            cT<T>* dst = (cT<T>*)J.out + (int64_t)b * J.out_bs;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                cT<T>* col = dst + (int64_t)(t + m * TPL) * J.out_ld + row0;
+#pragma unroll
+                for (int rr = 0; rr < 8; ++rr)
+                    if (row0 + rr < J.nrows) col[rr] = o[m][rr];
+            }
+        }
+    }
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(TileCfg<N>::THREADS)
+k_rows_c2r_t(RowJobs jobs, const cT<T>* __restrict__ tw)
+{
+    using C = TileCfg<N>;
+    constexpr int TPL = C::TPL;
+    constexpr int LL = lds_line_elems(N);
+    __shared__ cT<T> lds[C::LPB * LL + TableTwiddles<T, N>::size()];
+    TableTwiddles<T, N>::build(lds + C::LPB * LL, tw, threadIdx.x, C::THREADS);
+    __syncthreads();
+    const TableTwiddles<T, N> twl{lds + C::LPB * LL};
+    const int tl = threadIdx.x / TPL, t = threadIdx.x % TPL;
+    cT<T>* xl = lds + tl * LL;
+    const int total = jobs.total;
+    const int nb = (total + C::LPB - 1) / C::LPB;
+    for (int gb = xcd_order(blockIdx.x, gridDim.x); gb < nb; gb += gridDim.x) {
+        const int g = gb * C::LPB + tl;
+        const bool live = g < total;
+        const RowJob& J = jobs.j[find_job(jobs, live ? g : 0)];
+        const int gl = (live ? g : 0) - J.begin;
+        const int b = gl / J.bpb, row0 = (gl % J.bpb) * 8;
+        const cT<T>* src = (const cT<T>*)J.in + (int64_t)b * J.in_bs;
+        cT<T> c[4][8];   // c[m][row]: packed half spectrum at k = t + m TPL
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const cT<T>* col = src + (int64_t)(t + m * TPL) * J.in_ld + row0;
+#pragma unroll
+            for (int rr = 0; rr < 8; ++rr) c[m][rr] = (live && row0 + rr < J.nrows) ? col[rr] : mk<T>(0, 0);
+        }
+        T* dst = (T*)J.out + (int64_t)b * J.out_bs;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            // the pair's half spectra A (row 2p) and C (row 2p+1) at k < N/2
+            // go through LDS so that each thread can read its mirror positions
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                xl[lpad(t + m * TPL)] = c[m][2 * p];
+                xl[lpad(N / 2 + t + m * TPL)] = c[m][2 * p + 1];
+            }
+            __syncthreads();
+            cT<T> v[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int k = t + m * TPL;
+                cT<T> A, Cc;
+                if (k == 0 || k == N / 2) {
+                    const cT<T> pa = xl[lpad(0)], pc = xl[lpad(N / 2)];
+                    A = mk<T>(k == 0 ? pa.x : pa.y, 0);
+                    Cc = mk<T>(k == 0 ? pc.x : pc.y, 0);
+                } else if (k < N / 2) {
+                    A = c[m][2 * p];
+                    Cc = c[m][2 * p + 1];
+                } else {
+                    A = xl[lpad(N - k)];
+                    Cc = xl[lpad(N / 2 + N - k)];
+                    A.y = -A.y;
+                    Cc.y = -Cc.y;
+                }
+                v[m] = mk<T>(A.x - Cc.y, A.y + Cc.x);
+            }
+            fft_line<T, N, +1, false>(v, xl, twl, t);   // begins with a barrier
+            const int ra = row0 + 2 * p, rb = ra + 1;
+            if (live) {
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    const int x = t + m * TPL;
+                    if (x < J.nv) {
+                        if (ra < J.nrows) dst[(int64_t)ra * J.out_ld + x] = v[m].x;
+                        if (rb < J.nrows) dst[(int64_t)rb * J.out_ld + x] = v[m].y;
+                    }
+                }
             }
         }
     }
@@ -679,9 +853,20 @@ k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
 static int resident_blocks(const void* kernel, int threads)
 {
     int dev = 0, ncu = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 256;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || per < 1) per = 1;
+    if (hipGetDevice(&dev) != hipSuccess) { (void)hipGetLastError(); return 256; }
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        ncu = 256;
+    }
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0);
+    if (e != hipSuccess || per < 1) {
+        // a failed query must not leave its error for the launch check
+        (void)hipGetLastError();
+        if (std::getenv("BTTB_DEBUG"))
+            std::fprintf(stderr, "bttb: occupancy query failed (%s, per=%d, threads=%d)\n", hipGetErrorString(e),
+                         per, threads);
+        per = 1;
+    }
     return std::max(1, ncu * per);
 }
 
@@ -701,7 +886,8 @@ hipError_t launch_generate(const GenParams& P, int r0, int nl, double* out, hipS
 
 template <typename T> int row_group_rows(int N, int tile)
 {
-#define L_RT(NN) return tile == 2 ? RowCfg<T, NN, 2>::RT : RowCfg<T, NN, 4>::RT;
+    if (tile == 8) return 8;
+#define L_RT(NN) return tile == 1 ? RowCfg<T, NN, 1>::RT : tile == 2 ? RowCfg<T, NN, 2>::RT : RowCfg<T, NN, 4>::RT;
     switch (N) {
     case 8: L_RT(8) case 16: L_RT(16) case 32: L_RT(32) case 64: L_RT(64) case 128: L_RT(128)
     case 256: L_RT(256) case 512: L_RT(512) case 1024: L_RT(1024) case 2048: L_RT(2048)
@@ -753,11 +939,33 @@ static hipError_t launch_c2r_n(const RowJobs& jobs, const cT<T>* tw, hipStream_t
     return hipGetLastError();
 }
 
+template <typename TI, typename T, int NN>
+static hipError_t launch_r2c_t(const RowJobs& jobs, const cT<T>* tw, hipStream_t s)
+{
+    using C = TileCfg<NN>;
+    static int resident = 0;
+    if (!resident) resident = resident_blocks((const void*)k_rows_r2c_t<TI, T, NN>, C::THREADS);
+    const int nb = (jobs.total + C::LPB - 1) / C::LPB;
+    hipLaunchKernelGGL((k_rows_r2c_t<TI, T, NN>), dim3(std::min(nb, resident)), dim3(C::THREADS), 0, s, jobs, tw);
+    return hipGetLastError();
+}
+
+template <typename T, int NN>
+static hipError_t launch_c2r_t(const RowJobs& jobs, const cT<T>* tw, hipStream_t s)
+{
+    using C = TileCfg<NN>;
+    static int resident = 0;
+    if (!resident) resident = resident_blocks((const void*)k_rows_c2r_t<T, NN>, C::THREADS);
+    const int nb = (jobs.total + C::LPB - 1) / C::LPB;
+    hipLaunchKernelGGL((k_rows_c2r_t<T, NN>), dim3(std::min(nb, resident)), dim3(C::THREADS), 0, s, jobs, tw);
+    return hipGetLastError();
+}
+
 template <typename TI, typename T>
 hipError_t launch_rows_r2c(int N, int tile, const RowJobs& jobs, const cT<T>* tw, hipStream_t s)
 {
     if (jobs.total <= 0) return hipSuccess;
-#define L_R2C(NN) return tile == 2 ? launch_r2c_n<TI, T, NN, 2>(jobs, tw, s) : launch_r2c_n<TI, T, NN, 4>(jobs, tw, s);
+#define L_R2C(NN) return tile == 8 ? launch_r2c_t<TI, T, NN>(jobs, tw, s) : tile == 1 ? launch_r2c_n<TI, T, NN, 1>(jobs, tw, s) : tile == 2 ? launch_r2c_n<TI, T, NN, 2>(jobs, tw, s) : launch_r2c_n<TI, T, NN, 4>(jobs, tw, s);
     BTTB_LEN_SWITCH(N, L_R2C)
 #undef L_R2C
     return hipErrorInvalidValue;
@@ -767,7 +975,7 @@ template <typename T>
 hipError_t launch_rows_c2r(int N, int tile, const RowJobs& jobs, const cT<T>* tw, hipStream_t s)
 {
     if (jobs.total <= 0) return hipSuccess;
-#define L_C2R(NN) return tile == 2 ? launch_c2r_n<T, NN, 2>(jobs, tw, s) : launch_c2r_n<T, NN, 4>(jobs, tw, s);
+#define L_C2R(NN) return tile == 8 ? launch_c2r_t<T, NN>(jobs, tw, s) : tile == 1 ? launch_c2r_n<T, NN, 1>(jobs, tw, s) : tile == 2 ? launch_c2r_n<T, NN, 2>(jobs, tw, s) : launch_c2r_n<T, NN, 4>(jobs, tw, s);
     BTTB_LEN_SWITCH(N, L_C2R)
 #undef L_C2R
     return hipErrorInvalidValue;

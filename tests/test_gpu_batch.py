@@ -103,7 +103,8 @@ def test_autotune_choices_preserve_results_and_cache(torch_cuda, tmp_path, monke
     assert len(open(tmp_path / "tune.txt").read().splitlines()) == 1
     ms_, rs = _inputs(torch, [Plan(pr, "fp32")], 2, 11)
     base = Plan(pr, "fp32").generate()
-    for cfg in ({"row_tile": 2, "col_tile": 2, "layer_chunk": 8}, {"row_tile": 4, "col_tile": 2}, tuned):
+    for cfg in ({"row_tile": 2, "col_tile": 2, "layer_chunk": 8}, {"row_tile": 4, "col_tile": 2},
+                {"row_tile": 8}, {"row_tile": 8, "layer_chunk": 16}, tuned):
         p = Plan(dict(pr, **cfg), "fp32").generate()
         assert torch.equal(p.forward(ms_[0]), base.forward(ms_[0]))
         assert torch.equal(p.transpose(rs[0]), base.transpose(rs[0]))

@@ -193,8 +193,9 @@ EDGE = [
 
 @pytest.mark.parametrize("k", range(len(EDGE)))
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_edge_shapes(torch_cuda, orc, k, prec):
-    pr = EDGE[k]
+@pytest.mark.parametrize("row_tile", [4, 8])
+def test_edge_shapes(torch_cuda, orc, k, prec, row_tile):
+    pr = dict(EDGE[k], row_tile=row_tile)
     _say("edge shape", k, prec)
     P, G = _dense_ref(orc, pr)
     m = W.normal_model(pr, 1000 + k)
