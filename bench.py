@@ -67,6 +67,30 @@ def pair_bytes(pr, Nx, Ny, esz):
     return 2 * spec + 2 * nx * ny * nz * esz + 2 * sx * sy * esz
 
 
+def counter_traffic(kernel):
+    """Scaled HBM bytes (FETCH_SIZE + WRITE_SIZE, rocprofv3 PMC runs) of one
+    launch of `kernel`, from the committed profile summary -- only if the
+    kernel sources are unchanged since the counters were taken, else None."""
+    import glob
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "hbm_counters_gravity_1024_fp32.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"<!-- traffic-json: (.*?) -->", open(path).read())
+    if not m:
+        return None
+    info = json.loads(m.group(1))
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1912_06976_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        h.update(open(f, "rb").read())
+    if h.hexdigest() != info.get("source_sha256"):
+        return None
+    k = info.get("kernels", {}).get(kernel)
+    return None if k is None else k["read_bytes"] + k["write_bytes"]
+
+
 def run_gpu(torch, B, pr, prec, m_host, r_host, steps, warmup, want_kernels=True):
     dt = torch.float32 if prec == "fp32" else torch.float64
     plan = B.Plan(pr, prec)
@@ -175,7 +199,7 @@ def main():
     dom = max(kern, key=kern.get)
     ach = kb[dom] / (kern[dom] * 1e-3) / 1e9
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": counter_traffic(dom),
             "algorithmic_bytes": kb[dom], "avg_ms": round(kern[dom], 4)}
     pb = pair_bytes(pr, Nx, Ny, 4)
     result = {

@@ -106,8 +106,9 @@ typedef struct {
                                   layers); smaller chunks keep the per-layer intermediate
                                   in the device's last-level cache and shrink the
                                   workspace.  Results do not depend on it.              */
-    int32_t row_tile;          /* tuning: 0 (default) or 2 / 4 pairs of rows per block of
-                                  the row transforms                                  */
+    int32_t row_tile;          /* tuning: 0 (default) or 1 / 2 / 4 pairs of rows per
+                                  block of the row transforms staged through LDS, or 8:
+                                  tiles of 8 rows held per thread                     */
     int32_t col_tile;          /* tuning: 0 (default) or 1 / 2 times the default number of
                                   columns per block of the column transforms          */
 } bttb_problem_desc;
@@ -198,7 +199,7 @@ bttb_status bttb_batch_destroy(bttb_batch_t batch);
  * Autotuner (the analogue of FFTW's planner "wisdom" the paper's MATLAB
  * runs preload, Sec. 5): for one descriptor and right-hand-side count, time
  * the products on the device for every candidate kernel configuration
- * (row_tile in {2, 4}, col_tile in {1, 2}, layer_chunk in {0, 8, 16, 32}
+ * (row_tile in {2, 4, 8}, col_tile in {1, 2}, layer_chunk in {0, 8, 16, 32}
  * below nz) and return the descriptor with the fastest one filled in.
  * Results are cached in a text file (path: environment variable
  * BTTB_TUNE_CACHE, default $HOME/.cache/bttb_autotune.txt), keyed by the
