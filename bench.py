@@ -40,14 +40,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(pr, Nx, Ny, esz, nrhs=1):
+def spectra_bytes(pr, Nx, Ny, esz, form):
+    """Algorithmic bytes of the stored layer spectra a product reads once:
+    complex form nz * (Nx/2) * Ny complex values; real even form
+    nz * (Nx/2 + 1) * (Ny/2 + 1) real values."""
+    nz = pr["nz"]
+    if form == "real_even":
+        return nz * (Nx // 2 + 1) * (Ny // 2 + 1) * esz
+    return nz * (Nx // 2) * Ny * 2 * esz
+
+
+def kernel_bytes(pr, Nx, Ny, esz, form, nrhs=1):
     """Algorithmic HBM bytes per launch of each kernel of the two products:
-    compulsory reads and writes of its inputs, outputs and spectra."""
+    compulsory reads and writes of its inputs, outputs and spectra (packed
+    half spectra: Nx/2 complex columns)."""
     nx, ny, nz = W.dims(pr)
     sx, sy = pr["sx"], pr["sy"]
-    nc = Nx // 2 + 1
+    nc = Nx // 2
     c = 2 * esz
-    spec = nz * nc * Ny * c
+    spec = spectra_bytes(pr, Nx, Ny, esz, form)
     return {
         "fwd_rows_r2c": nrhs * nz * (ny * nx * esz + nc * ny * c),
         "fwd_cols_fft_mac": spec + nrhs * (nz * nc * ny * c + nc * sy * c),
@@ -58,13 +69,12 @@ def kernel_bytes(pr, Nx, Ny, esz, nrhs=1):
     }
 
 
-def pair_bytes(pr, Nx, Ny, esz):
+def pair_bytes(pr, Nx, Ny, esz, form):
     """Algorithmic bytes of one G m + G^T r pair: read m, spectra twice,
     write G^T r, read r, write d."""
     nx, ny, nz = W.dims(pr)
     sx, sy = pr["sx"], pr["sy"]
-    spec = nz * (Nx // 2 + 1) * Ny * 2 * esz
-    return 2 * spec + 2 * nx * ny * nz * esz + 2 * sx * sy * esz
+    return 2 * spectra_bytes(pr, Nx, Ny, esz, form) + 2 * nx * ny * nz * esz + 2 * sx * sy * esz
 
 
 def counter_traffic(kernel):
@@ -143,6 +153,8 @@ def main():
                          "default: the autotuner's choice")
     ap.add_argument("--row-tile", type=int, default=0, help="row kernel tile (2, 4 or 8); default: tuned")
     ap.add_argument("--col-tile", type=int, default=0, help="column kernel tile (1 or 2); default: tuned")
+    ap.add_argument("--spectrum-form", default="auto", choices=["auto", "complex", "real_even"],
+                    help="stored spectrum form (auto: real even for this gravity workload)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's default kernel configuration instead of the autotuner's")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -170,7 +182,7 @@ def main():
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}), flush=True)
         return
 
-    pr = W.gravity_1024()
+    pr = dict(W.gravity_1024(), spectrum_form=args.spectrum_form)
     tuned = None
     if not args.no_autotune:
         pr, tune_ms = B.bttb_autotune(pr, "fp32", nrhs=1)
@@ -194,14 +206,15 @@ def main():
     Nx, Ny = g32["plan"].nx_fft, g32["plan"].ny_fft
     ms = g32["ms"]
     value = cells / (ms * 1e-3)
-    kb = kernel_bytes(pr, Nx, Ny, 4)
+    form = g32["plan"].spectrum_form
+    kb = kernel_bytes(pr, Nx, Ny, 4, form)
     kern = g32["kernels"]
     dom = max(kern, key=kern.get)
     ach = kb[dom] / (kern[dom] * 1e-3) / 1e9
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": counter_traffic(dom),
             "algorithmic_bytes": kb[dom], "avg_ms": round(kern[dom], 4)}
-    pb = pair_bytes(pr, Nx, Ny, 4)
+    pb = pair_bytes(pr, Nx, Ny, 4, form)
     result = {
         "metric": METRIC, "value": value, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -209,7 +222,8 @@ def main():
         "config": {"workload": "gravity g_z 1000x1000 stations, 12-cell padding -> 1024x1024x128 prisms "
                                "of 25x25x20 m, 20 random ellipsoids; one G*m + one G^T*r",
                    "fft": "%dx%d" % (Nx, Ny), "nrhs": 1, "precision": "fp32 spectra/FFT/MAC, fp64 generator",
-                   "accumulation": "fp64 depth accumulator", "kernel_config": tuned or "default"},
+                   "accumulation": "fp64 depth accumulator", "spectrum_form": form,
+                   "kernel_config": tuned or "default"},
         "roofline": roof,
         "step_algorithmic_GBps": round(pb / (ms * 1e-3) / 1e9, 1),
         "step_algorithmic_bytes": pb,

@@ -79,6 +79,20 @@ typedef enum { BTTB_FP32 = 0, BTTB_FP64 = 1 } bttb_precision;
  * BTTB_ACC_PLAIN plain FP32 sums. */
 typedef enum { BTTB_ACC_DEFAULT = 0, BTTB_ACC_PLAIN = 1, BTTB_ACC_TWOSUM = 2, BTTB_ACC_WIDE = 3 } bttb_accumulation;
 
+/* Stored form of the layer spectra.
+ * BTTB_SPECTRUM_COMPLEX: the transform of the circulant generator of
+ *   Sec. 3 (eq. Tcircpadded), N_y x N_x / 2 complex values per layer.
+ * BTTB_SPECTRUM_REAL_EVEN: for the symmetric gravity kernel (entries even in
+ *   both cell offsets, Sec. 4.1: the symmetric BTTB case of sym_BTTBFFT), the
+ *   generator placed centred on offset 0 is even, so its transform is real
+ *   and even in both frequencies and a quarter of it, (N_x/2 + 1)(N_y/2 + 1)
+ *   real values per layer, holds all of it; the paddings become a phase
+ *   applied once per column.  Needs N_x >= 2 (s_x - 1 + max(pxl, pxr)) + 1
+ *   and the same in y (always true for equal paddings on both sides).
+ * BTTB_SPECTRUM_AUTO: REAL_EVEN where it applies, else COMPLEX.
+ * The results of both forms agree to rounding. */
+typedef enum { BTTB_SPECTRUM_AUTO = 0, BTTB_SPECTRUM_COMPLEX = 1, BTTB_SPECTRUM_REAL_EVEN = 2 } bttb_spectrum_form;
+
 /*
  * Problem description: the parameter set of the paper's Table 2
  * (prob_params, gsx/gsy/gsz, z_blocks, I, D, F).
@@ -111,6 +125,8 @@ typedef struct {
                                   tiles of 8 rows held per thread                     */
     int32_t col_tile;          /* tuning: 0 (default) or 1 / 2 times the default number of
                                   columns per block of the column transforms          */
+    int32_t spectrum_form;     /* bttb_spectrum_form; REAL_EVEN where it does not apply
+                                  is an UNSUPPORTED error                             */
 } bttb_problem_desc;
 
 typedef struct bttb_plan_s* bttb_plan_t;
@@ -129,14 +145,20 @@ bttb_status bttb_plan_destroy(bttb_plan_t plan);
 bttb_status bttb_plan_query(bttb_plan_t plan, int32_t nrhs, size_t* spectra_bytes,
                             size_t* workspace_bytes, int32_t* nx_fft, int32_t* ny_fft);
 
+/* The spectrum form the plan uses (BTTB_SPECTRUM_COMPLEX or
+ * BTTB_SPECTRUM_REAL_EVEN).  Errors: NULL_POINTER. */
+bttb_status bttb_plan_spectrum_form(bttb_plan_t plan, int32_t* form);
+
 /* Fill the caller's spectra buffer (device, spectra_bytes, 256-byte aligned):
  * the generator T_r of every layer is evaluated in FP64 from the closed-form
  * prism integrals (Sec. 4.1 Algorithm gravity, Sec. 4.2 Algorithm magnetic),
  * placed in the circulant (Sec. 3, eq. Tcircpadded / Tcircpaddedgeneral),
  * transformed with an FP64 2-D FFT, scaled by 1 / (Nx Ny) and rounded to the
- * plan precision (the transform of the paper's sym_BTTBFFT / BTTBFFT).  The
- * transpose uses the conjugate of the same spectra (for a real generator
- * the transform of the flipped generator of eq. Ttran is the conjugate).
+ * plan precision (the transform of the paper's sym_BTTBFFT / BTTBFFT), in
+ * the plan's spectrum form (BTTB_SPECTRUM_REAL_EVEN: the centred generator,
+ * the real parts of a quarter of its transform).  The transpose uses the
+ * conjugate of the same spectra (for a real generator the transform of the
+ * flipped generator of eq. Ttran is the conjugate).
  * workspace: device, >= workspace_bytes of bttb_plan_query(plan, 1, ...). */
 bttb_status bttb_kernel_generate(bttb_plan_t plan, void* spectra, void* workspace,
                                  size_t ws_bytes, void* stream);

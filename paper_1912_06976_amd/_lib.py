@@ -15,11 +15,12 @@ STATUS_NAMES = {0: "BTTB_OK", 1: "BTTB_ERR_INVALID_VALUE", 2: "BTTB_ERR_NULL_POI
 BTTB_GRAVITY_GZ, BTTB_MAGNETIC_TMI, BTTB_PROBE = 0, 1, 99
 BTTB_FP32, BTTB_FP64 = 0, 1
 BTTB_ACC_DEFAULT, BTTB_ACC_PLAIN, BTTB_ACC_TWOSUM, BTTB_ACC_WIDE = 0, 1, 2, 3
+BTTB_SPECTRUM_AUTO, BTTB_SPECTRUM_COMPLEX, BTTB_SPECTRUM_REAL_EVEN = 0, 1, 2
 
 #: every symbol include/bttb.h declares
 EXPORTS = ["bttb_plan_create", "bttb_plan_destroy", "bttb_plan_query", "bttb_kernel_generate",
            "bttb_forward", "bttb_transpose", "bttb_forward_profiled", "bttb_transpose_profiled",
-           "bttb_debug_generator", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
+           "bttb_debug_generator", "bttb_plan_spectrum_form", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
            "bttb_batch_destroy", "bttb_autotune_query", "bttb_autotune", "bttb_status_string",
            "bttb_last_error"]
 
@@ -43,6 +44,7 @@ class ProblemDesc(ctypes.Structure):
         ("nx_fft", ctypes.c_int32), ("ny_fft", ctypes.c_int32),
         ("accumulation", ctypes.c_int32), ("layer_chunk", ctypes.c_int32),
         ("row_tile", ctypes.c_int32), ("col_tile", ctypes.c_int32),
+        ("spectrum_form", ctypes.c_int32),
     ]
 
 
@@ -88,7 +90,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     L.bttb_last_error.restype = ctypes.c_char_p
     for name in ["bttb_plan_create", "bttb_plan_destroy", "bttb_plan_query", "bttb_kernel_generate",
                  "bttb_forward", "bttb_transpose", "bttb_forward_profiled", "bttb_transpose_profiled",
-                 "bttb_debug_generator", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
+                 "bttb_debug_generator", "bttb_plan_spectrum_form", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
                  "bttb_batch_destroy", "bttb_autotune_query", "bttb_autotune"]:
         getattr(L, name).restype = ctypes.c_int
     _handle = L

@@ -60,6 +60,9 @@ struct bttb_plan_s {
     int gen_batch;
     int tr_chunk;
     int row_tile, col_tile;      // kernel tile choices (see bttb_problem_desc)
+    int form;                    // FORM_COMPLEX or FORM_REAL_EVEN
+    int64_t ldr;                 // real even spectra: line stride (elements)
+    int bx, by;                  // real even spectra: largest |offset| used in x and y
 };
 
 namespace {
@@ -111,6 +114,9 @@ bttb_status validate_and_fill(const bttb_problem_desc* d, bttb_plan_s* P)
         return fail(BTTB_ERR_INVALID_VALUE, "row_tile must be 0, 1, 2, 4 or 8");
     if (d->col_tile != 0 && d->col_tile != 1 && d->col_tile != 2)
         return fail(BTTB_ERR_INVALID_VALUE, "col_tile must be 0, 1 or 2");
+    if (d->spectrum_form != BTTB_SPECTRUM_AUTO && d->spectrum_form != BTTB_SPECTRUM_COMPLEX &&
+        d->spectrum_form != BTTB_SPECTRUM_REAL_EVEN)
+        return fail(BTTB_ERR_INVALID_VALUE, "spectrum_form must be a bttb_spectrum_form value");
 
     const int64_t minx = std::max<int64_t>(8, d->sx + nx - 1), miny = std::max<int64_t>(8, d->sy + ny - 1);
     int64_t Nx = d->nx_fft, Ny = d->ny_fft;
@@ -163,9 +169,24 @@ bttb_status validate_and_fill(const bttb_problem_desc* d, bttb_plan_s* P)
         P->off_twx = off; off = align_up(off + (size_t)Nx * 8);
         P->off_twy = off; off = align_up(off + (size_t)Ny * 8);
     }
+    // real even form: the offsets i - p + pxl of the product (x; y alike)
+    // span [-(sx - 1 + pxr), sx - 1 + pxl]; the centred generator covers
+    // |offset| <= bx and must not wrap: 2 bx + 1 <= Nx
+    P->bx = d->sx - 1 + std::max(d->pxl, d->pxr);
+    P->by = d->sy - 1 + std::max(d->pyl, d->pyr);
+    const bool even_ok = d->problem == BTTB_GRAVITY_GZ && 2 * (int64_t)P->bx + 1 <= Nx && 2 * (int64_t)P->by + 1 <= Ny;
+    if (d->spectrum_form == BTTB_SPECTRUM_REAL_EVEN && !even_ok)
+        return fail(BTTB_ERR_UNSUPPORTED,
+                    "BTTB_SPECTRUM_REAL_EVEN needs the gravity kernel and nx_fft >= 2 (sx - 1 + max(pxl, pxr)) + 1, "
+                    "ny_fft >= 2 (sy - 1 + max(pyl, pyr)) + 1");
+    P->form = (even_ok && d->spectrum_form != BTTB_SPECTRUM_COMPLEX) ? FORM_REAL_EVEN : FORM_COMPLEX;
+    P->ldr = (Ny / 2 + 1 + 31) / 32 * 32;
     P->off_spec = off;
     const size_t csz = 2 * P->esz;
-    off = align_up(off + (size_t)P->nz * P->ncols * (size_t)Ny * csz);
+    if (P->form == FORM_REAL_EVEN)
+        off = align_up(off + (size_t)P->nz * (P->ncols + 1) * (size_t)P->ldr * P->esz);
+    else
+        off = align_up(off + (size_t)P->nz * P->ncols * (size_t)Ny * csz);
     P->spec_bytes = off;
     P->gen_batch = std::min(P->nz, MAX_GEN_BATCH);
     P->tr_chunk = d->layer_chunk > 0 ? std::min(d->layer_chunk, P->nz) : P->nz;
@@ -217,6 +238,9 @@ GenParams gen_params(const bttb_plan_s* P, int r0, int nl)
     g.dx = P->d.dx; g.dy = P->d.dy; g.h = P->d.station_height; g.scale = P->scale;
     for (int k = 0; k <= nl; ++k) g.z[k] = P->z[r0 + k];
     g.w = P->w;
+    g.sym = P->form == FORM_REAL_EVEN;
+    g.bx = P->bx;
+    g.by = P->by;
     return g;
 }
 
@@ -233,7 +257,7 @@ bttb_status run_generate(const bttb_plan_s* P, char* spec, char* ws, hipStream_t
     const WsLayout L = ws_layout(P, 1);
     double* g64 = (double*)(ws + L.gen_a);
     double2* w64 = (double2*)(ws + L.gen_b);
-    cT<T>* out = (cT<T>*)(spec + P->off_spec);
+    void* out = spec + P->off_spec;
     const double inv = 1.0 / ((double)P->Nx * (double)P->Ny);
     for (int r0 = 0; r0 < P->nz; r0 += P->gen_batch) {
         const int nl = std::min(P->gen_batch, P->nz - r0);
@@ -248,7 +272,7 @@ bttb_status run_generate(const bttb_plan_s* P, char* spec, char* ws, hipStream_t
         rj.total = rj.j[0].bpb * nl;
         if ((st = hip_check(launch_rows_r2c<double, double>(P->Nx, 4, rj, tw64x, s), "generator rows")) != BTTB_OK)
             return st;
-        if ((st = hip_check(launch_cols_spec<T>(P->Ny, w64, P->ncols, nl, out, r0, inv, tw64y, s),
+        if ((st = hip_check(launch_cols_spec<T>(P->Ny, w64, P->ncols, nl, out, r0, inv, tw64y, P->form, P->ldr, s),
                             "generator columns")) != BTTB_OK)
             return st;
     }
@@ -316,24 +340,28 @@ struct RowStage {
     }
 };
 
-// column jobs grouped by (N, accumulation, column tile): key N * 16 + acc * 4 + tile
+// column jobs grouped by (N, accumulation, column tile, spectrum form)
+struct ColKey {
+    int N, acc, tile, form;
+    bool operator==(const ColKey& o) const { return N == o.N && acc == o.acc && tile == o.tile && form == o.form; }
+};
+
 template <typename T>
 struct ColStage {
-    std::vector<int> keys;
+    std::vector<ColKey> keys;
     std::vector<std::vector<ColJob>> jobs;
     std::vector<std::vector<int>> work;
     std::vector<const cT<T>*> tw;
     // units: work items per (right-hand side, column block): 1 for the
     // forward kernel (one block each), the layers for the persistent
     // transpose kernel
-    void add(int N, int acc, int tile, const cT<T>* twp, const ColJob& j, int units = 1)
+    void add(const ColKey& key, const cT<T>* twp, const ColJob& j, int units = 1)
     {
-        const int key = N * 16 + acc * 4 + tile;
         size_t g = 0;
-        while (g < keys.size() && keys[g] != key) ++g;
+        while (g < keys.size() && !(keys[g] == key)) ++g;
         if (g == keys.size()) { keys.push_back(key); jobs.emplace_back(); work.emplace_back(); tw.push_back(twp); }
         ColJob jj = j;
-        const int cb = col_block_lines<T>(N, tile);
+        const int cb = col_block_lines<T>(key.N, key.tile);
         jj.nbx = (j.ncols + cb - 1) / cb;
         jobs[g].push_back(jj);
         work[g].push_back(jj.nbx * j.nrhs * units);
@@ -370,20 +398,42 @@ template <typename T>
 bttb_status run_cols(const ColStage<T>& st, bool fwd, hipStream_t s)
 {
     for (size_t g = 0; g < st.keys.size(); ++g) {
-        const int N = st.keys[g] / 16, acc = (st.keys[g] / 4) % 4, tile = st.keys[g] % 4;
+        const ColKey k = st.keys[g];
         const cT<T>* tw = st.tw[g];
         bttb_status r = launch_tables<ColJob, ColJobs>(st.jobs[g], st.work[g], [&](const ColJobs& t) {
-            if (!fwd) return launch_cols_tr<T>(N, tile, t, tw, s);
-            if constexpr (sizeof(T) == 8) return launch_cols_fwd<T, ACC_PLAIN>(N, tile, t, tw, s);
+            if (!fwd) return launch_cols_tr<T>(k.N, k.tile, k.form, t, tw, s);
+            if constexpr (sizeof(T) == 8) return launch_cols_fwd<T, ACC_PLAIN>(k.N, k.tile, k.form, t, tw, s);
             else {
-                if (acc == ACC_PLAIN) return launch_cols_fwd<T, ACC_PLAIN>(N, tile, t, tw, s);
-                if (acc == ACC_TWOSUM) return launch_cols_fwd<T, ACC_TWOSUM>(N, tile, t, tw, s);
-                return launch_cols_fwd<T, ACC_WIDE>(N, tile, t, tw, s);
+                if (k.acc == ACC_PLAIN) return launch_cols_fwd<T, ACC_PLAIN>(k.N, k.tile, k.form, t, tw, s);
+                if (k.acc == ACC_TWOSUM) return launch_cols_fwd<T, ACC_TWOSUM>(k.N, k.tile, k.form, t, tw, s);
+                return launch_cols_fwd<T, ACC_WIDE>(k.N, k.tile, k.form, t, tw, s);
             }
         }, fwd ? "forward columns" : "transpose columns");
         if (r != BTTB_OK) return r;
     }
     return BTTB_OK;
+}
+
+// a column job of plan P (the form-specific fields filled in)
+ColJob col_job(const bttb_plan_s* P, const void* a, const char* spec, void* b, int64_t lda, int64_t ldb, int na,
+               int nb, int r0, int nl, int nrhs)
+{
+    ColJob j{};
+    j.a = a;
+    j.spec = spec + P->off_spec;
+    j.b = b;
+    j.lda = lda;
+    j.ldb = ldb;
+    j.na = na;
+    j.nb = nb;
+    j.r0 = r0;
+    j.nl = nl;
+    j.ncols = P->ncols;
+    j.nrhs = nrhs;
+    j.px = P->d.pxl;
+    j.py = P->d.pyl;
+    j.lds = P->ldr;
+    return j;
 }
 
 template <typename T> const cT<T>* tw_x(const bttb_plan_s* P, const char* spec) { return (const cT<T>*)(spec + P->off_twx); }
@@ -404,8 +454,8 @@ bttb_status run_forward(const std::vector<Item>& items, hipStream_t s, hipEvent_
         r1.add(P->Nx, P->row_tile, tw_x<T>(P, it.spec),
                RowJob{it.in, X, (int64_t)P->nx * P->ny, P->nx, (int64_t)P->ncols * P->ny, P->ny, P->nx, P->ny, 0, 0},
                it.nrhs * P->nz);
-        c2.add(P->Ny, P->acc, P->col_tile, tw_y<T>(P, it.spec),
-               ColJob{X, it.spec + P->off_spec, Y, P->ny, P->sy, P->ny, P->sy, 0, P->nz, P->ncols, it.nrhs, 0, 0});
+        c2.add(ColKey{P->Ny, P->acc, P->col_tile, P->form}, tw_y<T>(P, it.spec),
+               col_job(P, X, it.spec, Y, P->ny, P->sy, P->ny, P->sy, 0, P->nz, it.nrhs));
         r3.add(P->Nx, P->row_tile, tw_x<T>(P, it.spec),
                RowJob{Y, it.out, (int64_t)P->ncols * P->sy, P->sy, (int64_t)P->sx * P->sy, P->sx, P->sx, P->sy, 0, 0},
                it.nrhs);
@@ -452,9 +502,8 @@ bttb_status run_transpose(const std::vector<Item>& items, hipStream_t s, hipEven
             const WsLayout L = ws_layout(P, it.nrhs);
             const cT<T>* R = (const cT<T>*)(it.ws + L.tr_r);
             cT<T>* Z = (cT<T>*)(it.ws + L.tr_z);
-            c2.add(P->Ny, 0, P->col_tile, tw_y<T>(P, it.spec),
-                   ColJob{R, it.spec + P->off_spec, Z, P->sy, P->ny, P->sy, P->ny, r0, nl, P->ncols, it.nrhs, 0, 0},
-                   nl);
+            c2.add(ColKey{P->Ny, 0, P->col_tile, P->form}, tw_y<T>(P, it.spec),
+                   col_job(P, R, it.spec, Z, P->sy, P->ny, P->sy, P->ny, r0, nl, it.nrhs), nl);
             T* out = (T*)it.out;
             if (nl == P->nz) {
                 r3.add(P->Nx, P->row_tile, tw_x<T>(P, it.spec),
@@ -636,6 +685,14 @@ bttb_status bttb_transpose_profiled(bttb_plan_t plan, const void* spectra, const
     } catch (...) {
         return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_transpose_profiled");
     }
+}
+
+bttb_status bttb_plan_spectrum_form(bttb_plan_t plan, int32_t* form)
+{
+    g_last_error.clear();
+    if (!plan || !form) return fail(BTTB_ERR_NULL_POINTER, "plan and form must not be NULL");
+    *form = plan->form == FORM_REAL_EVEN ? BTTB_SPECTRUM_REAL_EVEN : BTTB_SPECTRUM_COMPLEX;
+    return BTTB_OK;
 }
 
 bttb_status bttb_debug_generator(bttb_plan_t plan, int32_t layer, double* host_out, void* workspace,
@@ -842,7 +899,7 @@ std::string tune_key(const bttb_plan_s* P, int nrhs)
     for (char& c : arch)
         if (c == ' ') c = '_';
     std::ostringstream k;
-    k << "v1 " << P->d.problem << ' ' << P->d.precision << ' ' << P->sx << ' ' << P->sy << ' ' << P->nz << ' '
+    k << "v2 " << P->form << ' ' << P->d.problem << ' ' << P->d.precision << ' ' << P->sx << ' ' << P->sy << ' ' << P->nz << ' '
       << P->d.pxl << ' ' << P->d.pxr << ' ' << P->d.pyl << ' ' << P->d.pyr << ' ' << P->Nx << ' ' << P->Ny << ' '
       << P->acc << ' ' << nrhs << ' ' << arch << ' ' << ncu;
     return k.str();

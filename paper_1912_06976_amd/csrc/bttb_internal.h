@@ -7,6 +7,8 @@ namespace bttbk {
 
 enum { KIND_GRAVITY = 0, KIND_MAGNETIC = 1, KIND_PROBE = 99 };
 enum { ACC_PLAIN = 0, ACC_TWOSUM = 1, ACC_WIDE = 2 };
+// stored spectrum forms (see bttb_cols.hip)
+enum { FORM_COMPLEX = 0, FORM_REAL_EVEN = 1 };
 
 // weights G_1..G_5 of the magnetic corner terms
 struct MagWeights { double g[5]; };
@@ -20,6 +22,9 @@ struct GenParams {
     double dx, dy, h, scale;
     double z[MAX_GEN_BATCH + 1];   // depth edges z_{r0} .. z_{r0 + nl} of the batch
     MagWeights w;
+    // centred even placement (real even spectra): T[ay][ax] = h(|ax|, |ay|)
+    // for |ax| <= bx, |ay| <= by
+    int sym, bx, by;
 };
 
 // Work tables.  A launch of a row or column kernel processes every job of
@@ -53,6 +58,8 @@ struct ColJob {
     int ncols, nrhs;
     int nbx;              // column blocks per right-hand-side block
     int begin;            // first global block index of this job
+    int px, py;           // real even spectra: phase offsets (pxl, pyl)
+    int64_t lds;          // real even spectra: line stride (elements)
 };
 struct ColJobs {
     ColJob j[MAX_JOBS];
@@ -74,12 +81,15 @@ template <typename TI, typename T>
 hipError_t launch_rows_r2c(int N, int tile, const RowJobs& jobs, const cT<T>* tw, hipStream_t s);
 template <typename T>
 hipError_t launch_rows_c2r(int N, int tile, const RowJobs& jobs, const cT<T>* tw, hipStream_t s);
+// spectra of nl generator layers (row-transformed, packed) into layers
+// [r0, r0 + nl) of `spec` in the given form (ldr: line stride of the real
+// even form)
 template <typename T>
-hipError_t launch_cols_spec(int N, const double2* in, int ncols, int nl, cT<T>* spec, int r0,
-                            double scale, const double2* tw, hipStream_t s);
+hipError_t launch_cols_spec(int N, const double2* in, int ncols, int nl, void* spec, int r0,
+                            double scale, const double2* tw, int form, int64_t ldr, hipStream_t s);
 template <typename T, int ACC>
-hipError_t launch_cols_fwd(int N, int tile, const ColJobs& jobs, const cT<T>* tw, hipStream_t s);
+hipError_t launch_cols_fwd(int N, int tile, int form, const ColJobs& jobs, const cT<T>* tw, hipStream_t s);
 template <typename T>
-hipError_t launch_cols_tr(int N, int tile, const ColJobs& jobs, const cT<T>* tw, hipStream_t s);
+hipError_t launch_cols_tr(int N, int tile, int form, const ColJobs& jobs, const cT<T>* tw, hipStream_t s);
 
 }  // namespace bttbk

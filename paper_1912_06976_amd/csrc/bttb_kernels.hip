@@ -10,24 +10,12 @@
 //                    ([kx][row]) through an LDS tile
 //   k_cols_spec      FP64 column transforms of the generator -> stored spectra
 //                    (scaled by 1 / (Nx Ny), rounded to the working precision)
-//   k_cols_fwd_mac   forward product: per column kx, the depth loop
-//                    A += T^_r * FFT_y(X_r) with an extended accumulator, then
-//                    one inverse FFT_y (eq. GrviaT summed over layers)
-//   k_cols_tr_mac    transpose product: R^ = FFT_y(R) once per column, then per
-//                    layer IFFT_y(conj(T^_r) R^)
 //   k_rows_c2r       half spectra ([kx][row]) -> real rows along x, two rows per
 //                    complex transform, extraction of the leading columns
 //
-// All kernels take caller-owned device buffers; none allocates.
-#include <hip/hip_runtime.h>
-#include <stdint.h>
-
-#include <algorithm>
-#include <cstdio>
-#include <cstdlib>
-
-#include "fft_core.h"
-#include "bttb_internal.h"
+// The column kernels of the products are in bttb_cols.hip.  All kernels take
+// caller-owned device buffers; none allocates.
+#include "kern_common.h"
 
 namespace bttbk {
 
@@ -86,6 +74,9 @@ __device__ __forceinline__ double corner_tmi(double x, double y, double z, const
 // h_r(dx, dy) is the prism integral over x in [(dx-1/2), (dx+1/2)] Dx,
 // y in [(dy-1/2), (dy+1/2)] Dy, z in [z_r + h, z_{r+1} + h]: the entry of
 // G for a station and a prism offset by (dx, dy) cells (Sec. 2.1.1-2.1.2).
+// Centred placement (P.sym, for a kernel even in dx and dy): T_r[Y][X] =
+// h_r(|ax|, |ay|) for |ax| <= bx, |ay| <= by with ax = X or X - Nx in
+// (-Nx/2, Nx/2]; the product's generator is this one shifted by (pxl, pyl).
 __global__ void k_generate(GenParams P, int r0, double* __restrict__ out)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -93,11 +84,21 @@ __global__ void k_generate(GenParams P, int r0, double* __restrict__ out)
     if (idx >= per) return;
     const int r = r0 + blockIdx.y;
     const int X = (int)(idx % P.Nx), Y = (int)(idx / P.Nx);
-    int ax = X <= P.sx - 1 ? X : (X >= P.Nx - (P.nx - 1) ? X - P.Nx : INT32_MIN);
-    int ay = Y <= P.sy - 1 ? Y : (Y >= P.Ny - (P.ny - 1) ? Y - P.Ny : INT32_MIN);
+    bool inside;
+    int ox, oy;
+    if (P.sym) {
+        ox = X <= P.Nx / 2 ? X : P.Nx - X;
+        oy = Y <= P.Ny / 2 ? Y : P.Ny - Y;
+        inside = ox <= P.bx && oy <= P.by;
+    } else {
+        const int ax = X <= P.sx - 1 ? X : (X >= P.Nx - (P.nx - 1) ? X - P.Nx : INT32_MIN);
+        const int ay = Y <= P.sy - 1 ? Y : (Y >= P.Ny - (P.ny - 1) ? Y - P.Ny : INT32_MIN);
+        inside = ax != INT32_MIN && ay != INT32_MIN;
+        ox = inside ? -ax - P.pxl : 0;
+        oy = inside ? -ay - P.pyl : 0;
+    }
     double val = 0.0;
-    if (ax != INT32_MIN && ay != INT32_MIN) {
-        const int ox = -ax - P.pxl, oy = -ay - P.pyl;
+    if (inside) {
         if (P.kind == KIND_PROBE) {
             val = (double)ox + 4096.0 * (double)oy + 16777216.0 * (double)r;
         } else {
@@ -135,14 +136,6 @@ __global__ void k_generate(GenParams P, int r0, double* __restrict__ out)
 // column kernels separate them with the mirror index -k when they need them
 // individually (block 0 only).  The number of columns is exactly N/2.
 
-// hardware block b -> logical block such that the blocks that the hardware
-// places on one XCD (b mod 8) get consecutive logical indices
-__device__ __forceinline__ int xcd_order(int b, int G)
-{
-    const int xcd = b & 7, k = b >> 3;
-    const int per = G >> 3, rem = G & 7;
-    return xcd < rem ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
-}
 
 // ---------------------------------------------------------------------------
 // row transforms
@@ -170,14 +163,6 @@ template <typename T, int N, int P0 = 4> struct RowCfg {
 // The loads of the next group are issued before the current group is
 // transformed, so memory latency overlaps the FFT.
 
-// index of the job whose work range [begin, next begin) contains w
-template <typename JT> __device__ __forceinline__ int find_job(const JT& js, int w)
-{
-    int k = 0;
-    for (int i = 1; i < js.njobs; ++i)
-        if (w >= js.j[i].begin) k = i;
-    return k;
-}
 
 // Row transform, real -> packed half spectra, over every job of the table.
 // Job input: batch b, row y, column x at in[b * in_bs + y * in_ld + x],
@@ -521,26 +506,19 @@ k_rows_c2r_t(RowJobs jobs, const cT<T>* __restrict__ tw)
 // ---------------------------------------------------------------------------
 // column transforms
 // ---------------------------------------------------------------------------
-// minimum waves per SIMD requested for the column kernels (bounds the VGPRs
-// the compiler may use: 512 / waves)
-#ifndef BTTB_COL_WAVES
-#define BTTB_COL_WAVES 2
-#endif
-// CM: multiplier of the columns per block (a tuning choice, 1 or 2)
-template <int N, int CM = 1> struct ColCfg {
-    static constexpr int TPL = N / 8;
-    static constexpr int CPW = (TPL >= 256 ? 1 : 256 / TPL) * CM;   // columns per block
-    static constexpr int THREADS = CPW * TPL;
-};
-
 // spectra from the FP64 generator: in[(l * ncols + kx) * N + y] (l = layer in
-// batch, packed half spectra along x) -> spec[((r0 + l) * ncols + kx) * N + ky]
-// = FFT_y(in) * scale (column 0 becomes T^[0] + i T^[N/2], the packed pair of
-// Hermitian columns)
+// batch, packed half spectra along x) -> FFT_y(in) * scale, stored as
+//   FORM_COMPLEX:   spec[((r0 + l) * ncols + kx) * N + ky] (column 0 becomes
+//                   T^[0] + i T^[N/2], the packed pair of Hermitian columns)
+//   FORM_REAL_EVEN: the real parts for ky in [0, N/2] at
+//                   spec[((r0 + l) * (ncols + 1) + kx) * ldr + ky], with
+//                   kx = Nx/2 (the imaginary part of column 0) in line ncols.
+//                   For the centred even generator the transform is real up to
+//                   rounding (its imaginary parts are dropped).
 template <typename T, int N>
 __global__ void __launch_bounds__(ColCfg<N>::THREADS)
-k_cols_spec(const double2* __restrict__ in, int ncols, cT<T>* __restrict__ spec, int r0, double scale,
-            const double2* __restrict__ tw)
+k_cols_spec(const double2* __restrict__ in, int ncols, void* __restrict__ spec, int r0, double scale,
+            const double2* __restrict__ tw, int form, int64_t ldr)
 {
     using C = ColCfg<N>;
     constexpr int TPL = C::TPL;
@@ -557,276 +535,18 @@ k_cols_spec(const double2* __restrict__ in, int ncols, cT<T>* __restrict__ spec,
     twl.load(tw, t);
     fft_line<double, N, -1, false>(v, lds + cl * lds_line_elems(N), twl, t);
     if (!ok) return;
-    cT<T>* dst = spec + ((int64_t)(r0 + l) * ncols + col) * N;
+    if (form == FORM_COMPLEX) {
+        cT<T>* dst = (cT<T>*)spec + ((int64_t)(r0 + l) * ncols + col) * N;
 #pragma unroll
-    for (int m = 0; m < 8; ++m) dst[t + m * TPL] = mk<T>((T)(v[m].x * scale), (T)(v[m].y * scale));
-}
-
-// depth accumulators ------------------------------------------------------
-template <typename T, int ACC> struct Acc;
-template <typename T> struct Acc<T, ACC_PLAIN> {
-    cT<T> s;
-    __device__ __forceinline__ void zero() { s = mk<T>(0, 0); }
-    __device__ __forceinline__ void add(cT<T> p) { s.x += p.x; s.y += p.y; }
-    __device__ __forceinline__ cT<T> get() const { return s; }
-};
-// compensated (TwoSum) accumulation in the working precision
-template <typename T> struct Acc<T, ACC_TWOSUM> {
-    cT<T> s, c;
-    __device__ __forceinline__ void zero() { s = mk<T>(0, 0); c = mk<T>(0, 0); }
-    __device__ __forceinline__ static void two_sum(T& s, T& c, T p) {
-        const T n = s + p;
-        const T bp = n - s;
-        const T e = (s - (n - bp)) + (p - bp);
-        s = n;
-        c += e;
-    }
-    __device__ __forceinline__ void add(cT<T> p) { two_sum(s.x, c.x, p.x); two_sum(s.y, c.y, p.y); }
-    __device__ __forceinline__ cT<T> get() const { return mk<T>(s.x + c.x, s.y + c.y); }
-};
-// FP64 accumulation of FP32 products
-template <typename T> struct Acc<T, ACC_WIDE> {
-    double sx, sy;
-    __device__ __forceinline__ void zero() { sx = 0.0; sy = 0.0; }
-    __device__ __forceinline__ void add(cT<T> p) { sx += (double)p.x; sy += (double)p.y; }
-    __device__ __forceinline__ cT<T> get() const { return mk<T>((T)sx, (T)sy); }
-};
-
-// Column 0 of the packed format holds z = A + i B with A, B the transforms
-// of two real sequences (Hermitian).  With zr = z at -k:
-//   A = (z + conj zr) / 2,  B = (z - conj zr) / (2 i).
-template <typename T> __device__ __forceinline__ cT<T> herm_a(cT<T> z, cT<T> zr) {
-    return mk<T>((T)0.5 * (z.x + zr.x), (T)0.5 * (z.y - zr.y));
-}
-template <typename T> __device__ __forceinline__ cT<T> herm_b(cT<T> z, cT<T> zr) {
-    return mk<T>((T)0.5 * (z.y + zr.y), (T)0.5 * (zr.x - z.x));
-}
-
-// Store two register lines (positions t + m TPL) into two LDS line buffers so
-// that their values at the mirror positions -k can be read back one at a
-// time.  Contains barriers: every thread of the block calls it; only
-// `active` threads write.
-template <typename T, int N>
-__device__ __forceinline__ void stage_pair(const cT<T> (&u)[8], const cT<T> (&w)[8], cT<T>* bu, cT<T>* bw,
-                                           int t, bool active)
-{
-    constexpr int TPL = N / 8;
-    __syncthreads();
-    if (active) {
+        for (int m = 0; m < 8; ++m) dst[t + m * TPL] = mk<T>((T)(v[m].x * scale), (T)(v[m].y * scale));
+    } else {
+        T* base = (T*)spec + (int64_t)(r0 + l) * (ncols + 1) * ldr;
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
-            bu[lpad(t + m * TPL)] = u[m];
-            bw[lpad(t + m * TPL)] = w[m];
-        }
-    }
-    __syncthreads();
-}
-template <int N> __device__ __forceinline__ int mirror_idx(int t, int m) {
-    return lpad((N - t - m * (N / 8)) & (N - 1));
-}
-
-// Forward column pass over every job of the table (one block per CPW
-// columns of one right-hand-side block of one job).  Job: a = X with
-// X[((q * nz + r) * ncols + kx) * lda + y], y < na = ny (packed row-pass
-// output), nl = nz layers; b = Y with Y[(q * ncols + kx) * ldb + y], y < nb = sy.
-template <typename T, int N, int NR, int ACC, int CM>
-__global__ void __launch_bounds__((ColCfg<N, CM>::THREADS), BTTB_COL_WAVES)
-k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
-{
-    using C = ColCfg<N, CM>;
-    constexpr int TPL = C::TPL;
-    constexpr int LL = lds_line_elems(N);
-    __shared__ cT<T> lds[(C::CPW + 1) * LL];
-    const ColJob& J = jobs.j[find_job(jobs, blockIdx.x)];
-    const cT<T>* __restrict__ X = (const cT<T>*)J.a;
-    const cT<T>* __restrict__ spec = (const cT<T>*)J.spec;
-    cT<T>* __restrict__ Y = (cT<T>*)J.b;
-    const int64_t ldx = J.lda, ldy = J.ldb;
-    const int ny = J.na, sy = J.nb, nz = J.nl, ncols = J.ncols, nrhs = J.nrhs;
-    const int lb = blockIdx.x - J.begin, cb = lb % J.nbx;
-    const int cl = threadIdx.x / TPL, t = threadIdx.x % TPL;
-    const int col = cb * C::CPW + cl;
-    const int q0 = (lb / J.nbx) * NR;
-    const bool ok = col < ncols;
-    const bool packed_blk = cb == 0;              // block holding column 0
-    const bool packed = packed_blk && cl == 0;
-    cT<T>* xl = lds + cl * LL;
-    cT<T>* xs2 = lds + C::CPW * LL;               // second buffer (column 0)
-    LineTwiddles<T, N> twl;
-    twl.load(tw, t);
-    Acc<T, ACC> acc[NR][8];
-#pragma unroll
-    for (int q = 0; q < NR; ++q)
-#pragma unroll
-        for (int m = 0; m < 8; ++m) acc[q][m].zero();
-    const bool zhi = ny <= N / 2;
-    const int ccol = ok ? col : 0;
-    // software pipeline: the next layer's spectra and input columns are
-    // loaded while the current layer is transformed
-    cT<T> tn[8], xn[NR][8];
-    auto load_layer = [&](int r) {
-        const cT<T>* sp = spec + ((int64_t)r * ncols + ccol) * N;
-#pragma unroll
-        for (int m = 0; m < 8; ++m) tn[m] = sp[t + m * TPL];
-#pragma unroll
-        for (int q = 0; q < NR; ++q) {
-            const int qq = q0 + q;
-            const cT<T>* xs = X + (((int64_t)(qq < nrhs ? qq : 0) * nz + r) * ncols + ccol) * ldx;
-#pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                const int y = t + m * TPL;
-                xn[q][m] = (ok && qq < nrhs && y < ny) ? xs[y] : mk<T>(0, 0);
-            }
-        }
-    };
-    load_layer(0);
-    for (int r = 0; r < nz; ++r) {
-        cT<T> tv[8], v[NR][8];
-#pragma unroll
-        for (int m = 0; m < 8; ++m) tv[m] = tn[m];
-#pragma unroll
-        for (int q = 0; q < NR; ++q)
-#pragma unroll
-            for (int m = 0; m < 8; ++m) v[q][m] = xn[q][m];
-        if (r + 1 < nz) load_layer(r + 1);
-#pragma unroll
-        for (int q = 0; q < NR; ++q) {
-            if (zhi) fft_line<T, N, -1, true>(v[q], xl, twl, t);
-            else fft_line<T, N, -1, false>(v[q], xl, twl, t);
-            if (packed_blk) {
-                stage_pair<T, N>(v[q], tv, xl, xs2, t, packed);
-                if (packed) {
-                    // column 0 carries bins 0 and N/2: accumulate
-                    // T0 F0 + i T1 F1 of the separated Hermitian parts
-#pragma unroll
-                    for (int m = 0; m < 8; ++m) {
-                        const int mi = mirror_idx<N>(t, m);
-                        const cT<T> vr = xl[mi], tr = xs2[mi];
-                        const cT<T> p0 = cmul<T>(herm_a<T>(tv[m], tr), herm_a<T>(v[q][m], vr));
-                        const cT<T> p1 = cmul<T>(herm_b<T>(tv[m], tr), herm_b<T>(v[q][m], vr));
-                        acc[q][m].add(mk<T>(p0.x - p1.y, p0.y + p1.x));
-                    }
-                    continue;
-                }
-            }
-#pragma unroll
-            for (int m = 0; m < 8; ++m) acc[q][m].add(cmul<T>(tv[m], v[q][m]));
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < NR; ++q) {
-        const int qq = q0 + q;
-        cT<T> w[8];
-#pragma unroll
-        for (int m = 0; m < 8; ++m) w[m] = acc[q][m].get();
-        fft_line<T, N, +1, false>(w, xl, twl, t);
-        if (ok && qq < nrhs) {
-            cT<T>* ys = Y + ((int64_t)qq * ncols + col) * ldy;
-#pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                const int y = t + m * TPL;
-                if (y < sy) ys[y] = w[m];
-            }
-        }
-    }
-}
-
-// Transpose column pass over every job of the table, layers [r0, r0 + nl).
-// Job: a = R with R[(q * ncols + kx) * lda + y], y < na = sy (packed row-pass
-// output of the data); b = Z with Z[((q * nl + r - r0) * ncols + kx) * ldb + y],
-// y < nb = ny.
-// The kernel is persistent and balanced: the work of all jobs is the list of
-// units (job, right-hand side q, column block cb, layer l), layer fastest,
-// and block w processes the contiguous range [w U / G, (w + 1) U / G).  A
-// block recomputes R^ = FFT_y(R) whenever its range enters a new column
-// block (at most a few times), so every block gets the same number of layers
-// whatever the number of resident blocks.
-template <typename T, int N, int NR, int CM>
-__global__ void __launch_bounds__((ColCfg<N, CM>::THREADS), BTTB_COL_WAVES)
-k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
-{
-    using C = ColCfg<N, CM>;
-    constexpr int TPL = C::TPL;
-    constexpr int LL = lds_line_elems(N);
-    __shared__ cT<T> lds[(C::CPW + 1) * LL];
-    const int cl = threadIdx.x / TPL, t = threadIdx.x % TPL;
-    cT<T>* xl = lds + cl * LL;
-    cT<T>* xs2 = lds + C::CPW * LL;
-    LineTwiddles<T, N> twl;
-    twl.load(tw, t);
-    const int64_t U = jobs.total, G = gridDim.x;
-    const int u0 = (int)((int64_t)blockIdx.x * U / G), u1 = (int)((int64_t)(blockIdx.x + 1) * U / G);
-    // unit u -> (job k, key = q * nbx + cb, layer l)
-    auto decode = [&](int u, int& k, int& key, int& l) {
-        k = find_job(jobs, u);
-        const int lu = u - jobs.j[k].begin;
-        l = lu % jobs.j[k].nl;
-        key = lu / jobs.j[k].nl;
-    };
-    cT<T> tn[8];
-    auto load_spec = [&](int u) {
-        int k, key, l;
-        decode(u, k, key, l);
-        const ColJob& J = jobs.j[k];
-        const int col = (key % J.nbx) * C::CPW + cl;
-        const cT<T>* sp = (const cT<T>*)J.spec + ((int64_t)(J.r0 + l) * J.ncols + (col < J.ncols ? col : 0)) * N;
-#pragma unroll
-        for (int m = 0; m < 8; ++m) tn[m] = sp[t + m * TPL];
-    };
-    int cur_k = -1, cur_key = -1;
-    cT<T> rh[8];
-    if (u0 < u1) load_spec(u0);
-    for (int u = u0; u < u1; ++u) {
-        int k, key, l;
-        decode(u, k, key, l);
-        const ColJob& J = jobs.j[k];
-        const int cb = key % J.nbx, q = key / J.nbx;
-        const int col = cb * C::CPW + cl;
-        const bool ok = col < J.ncols;
-        const bool packed_blk = cb == 0;
-        const bool packed = packed_blk && cl == 0;
-        cT<T> tv[8];
-#pragma unroll
-        for (int m = 0; m < 8; ++m) tv[m] = tn[m];
-        if (u + 1 < u1) load_spec(u + 1);
-        if (k != cur_k || key != cur_key) {
-            // R^ of this column: FFT_y of the packed row-pass output of the data
-            const cT<T>* rs = (const cT<T>*)J.a + ((int64_t)q * J.ncols + (ok ? col : 0)) * J.lda;
-#pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                const int y = t + m * TPL;
-                rh[m] = (ok && y < J.na) ? rs[y] : mk<T>(0, 0);
-            }
-            if (J.na <= N / 2) fft_line<T, N, -1, true>(rh, xl, twl, t);
-            else fft_line<T, N, -1, false>(rh, xl, twl, t);
-            cur_k = k;
-            cur_key = key;
-        }
-        cT<T> v[8];
-#pragma unroll
-        for (int m = 0; m < 8; ++m) v[m] = cmulc<T>(rh[m], tv[m]);
-        if (packed_blk) {
-            stage_pair<T, N>(rh, tv, xl, xs2, t, packed);
-            if (packed) {
-                // column 0: conj(T0) R0 + i conj(T1) R1
-#pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    const int mi = mirror_idx<N>(t, m);
-                    const cT<T> rr = xl[mi], tr = xs2[mi];
-                    const cT<T> p0 = cmulc<T>(herm_a<T>(rh[m], rr), herm_a<T>(tv[m], tr));
-                    const cT<T> p1 = cmulc<T>(herm_b<T>(rh[m], rr), herm_b<T>(tv[m], tr));
-                    v[m] = mk<T>(p0.x - p1.y, p0.y + p1.x);
-                }
-            }
-        }
-        fft_line<T, N, +1, false>(v, xl, twl, t);
-        if (ok) {
-            cT<T>* zs = (cT<T>*)J.b + (((int64_t)q * J.nl + l) * J.ncols + col) * J.ldb;
-#pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                const int y = t + m * TPL;
-                if (y < J.nb) zs[y] = v[m];
-            }
+            const int y = t + m * TPL;
+            if (y > N / 2) continue;
+            base[(int64_t)col * ldr + y] = (T)(v[m].x * scale);
+            if (col == 0) base[(int64_t)ncols * ldr + y] = (T)(v[m].y * scale);
         }
     }
 }
@@ -834,41 +554,6 @@ k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
 // ---------------------------------------------------------------------------
 // launchers (dispatch on the transform lengths)
 // ---------------------------------------------------------------------------
-#define BTTB_LEN_SWITCH(n, MACRO) \
-    switch (n) {                  \
-    case 8: MACRO(8); break;      \
-    case 16: MACRO(16); break;    \
-    case 32: MACRO(32); break;    \
-    case 64: MACRO(64); break;    \
-    case 128: MACRO(128); break;  \
-    case 256: MACRO(256); break;  \
-    case 512: MACRO(512); break;  \
-    case 1024: MACRO(1024); break;\
-    case 2048: MACRO(2048); break;\
-    case 4096: MACRO(4096); break;\
-    default: return hipErrorInvalidValue; }
-
-// blocks of `kernel` that are resident on the whole current device at once
-// (occupancy per CU times the number of CUs); at least 1
-static int resident_blocks(const void* kernel, int threads)
-{
-    int dev = 0, ncu = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess) { (void)hipGetLastError(); return 256; }
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-        (void)hipGetLastError();
-        ncu = 256;
-    }
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0);
-    if (e != hipSuccess || per < 1) {
-        // a failed query must not leave its error for the launch check
-        (void)hipGetLastError();
-        if (std::getenv("BTTB_DEBUG"))
-            std::fprintf(stderr, "bttb: occupancy query failed (%s, per=%d, threads=%d)\n", hipGetErrorString(e),
-                         per, threads);
-        per = 1;
-    }
-    return std::max(1, ncu * per);
-}
 
 hipError_t launch_twiddles(double2* t64, float2* t32, int n, hipStream_t s)
 {
@@ -898,11 +583,6 @@ template <typename T> int row_group_rows(int N, int tile)
 template int row_group_rows<float>(int, int);
 template int row_group_rows<double>(int, int);
 
-// a column tile of 2 is used only where its LDS fits in 160 KB
-template <typename T, int NN> constexpr bool col_tile2_fits()
-{
-    return (ColCfg<NN, 2>::CPW + 1) * lds_line_elems(NN) * (int)sizeof(cT<T>) <= 160 * 1024;
-}
 
 template <typename T> int col_block_lines(int N, int tile)
 {
@@ -982,64 +662,18 @@ hipError_t launch_rows_c2r(int N, int tile, const RowJobs& jobs, const cT<T>* tw
 }
 
 template <typename T>
-hipError_t launch_cols_spec(int N, const double2* in, int ncols, int nl, cT<T>* spec, int r0,
-                            double scale, const double2* tw, hipStream_t s)
+hipError_t launch_cols_spec(int N, const double2* in, int ncols, int nl, void* spec, int r0,
+                            double scale, const double2* tw, int form, int64_t ldr, hipStream_t s)
 {
 #define L_SPEC(NN)                                                                         \
     {                                                                                      \
         using C = ColCfg<NN>;                                                              \
         dim3 grid((ncols + C::CPW - 1) / C::CPW, nl);                                      \
         hipLaunchKernelGGL((k_cols_spec<T, NN>), grid, dim3(C::THREADS), 0, s, in, ncols, spec, \
-                           r0, scale, tw);                                                 \
+                           r0, scale, tw, form, ldr);                                      \
     }
     BTTB_LEN_SWITCH(N, L_SPEC)
 #undef L_SPEC
-    return hipGetLastError();
-}
-
-template <typename T, int ACC>
-hipError_t launch_cols_fwd(int N, int tile, const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
-{
-    if (jobs.total <= 0) return hipSuccess;
-#define L_FWD(NN)                                                                          \
-    if constexpr (col_tile2_fits<T, NN>()) {                                               \
-        if (tile == 2) {                                                                   \
-            hipLaunchKernelGGL((k_cols_fwd_mac<T, NN, 1, ACC, 2>), dim3(jobs.total), dim3(ColCfg<NN, 2>::THREADS), \
-                               0, s, jobs, tw);                                            \
-            break;                                                                         \
-        }                                                                                  \
-    }                                                                                      \
-    hipLaunchKernelGGL((k_cols_fwd_mac<T, NN, 1, ACC, 1>), dim3(jobs.total), dim3(ColCfg<NN, 1>::THREADS), 0, \
-                       s, jobs, tw);
-    BTTB_LEN_SWITCH(N, L_FWD)
-#undef L_FWD
-    return hipGetLastError();
-}
-
-// persistent: as many blocks as are resident at once (at most one per unit)
-template <typename T, int NN, int CM>
-static void launch_tr_n(const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
-{
-    static int resident = 0;
-    if (!resident) resident = resident_blocks((const void*)k_cols_tr_mac<T, NN, 1, CM>, ColCfg<NN, CM>::THREADS);
-    hipLaunchKernelGGL((k_cols_tr_mac<T, NN, 1, CM>), dim3(std::min(jobs.total, resident)),
-                       dim3(ColCfg<NN, CM>::THREADS), 0, s, jobs, tw);
-}
-
-template <typename T>
-hipError_t launch_cols_tr(int N, int tile, const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
-{
-    if (jobs.total <= 0) return hipSuccess;
-#define L_TR(NN)                                                                           \
-    if constexpr (col_tile2_fits<T, NN>()) {                                               \
-        if (tile == 2) {                                                                   \
-            launch_tr_n<T, NN, 2>(jobs, tw, s);                                            \
-            break;                                                                         \
-        }                                                                                  \
-    }                                                                                      \
-    launch_tr_n<T, NN, 1>(jobs, tw, s);
-    BTTB_LEN_SWITCH(N, L_TR)
-#undef L_TR
     return hipGetLastError();
 }
 
@@ -1048,15 +682,9 @@ template hipError_t launch_rows_r2c<double, double>(int, int, const RowJobs&, co
 template hipError_t launch_rows_r2c<float, float>(int, int, const RowJobs&, const float2*, hipStream_t);
 template hipError_t launch_rows_c2r<double>(int, int, const RowJobs&, const double2*, hipStream_t);
 template hipError_t launch_rows_c2r<float>(int, int, const RowJobs&, const float2*, hipStream_t);
-template hipError_t launch_cols_spec<double>(int, const double2*, int, int, double2*, int, double,
-                                             const double2*, hipStream_t);
-template hipError_t launch_cols_spec<float>(int, const double2*, int, int, float2*, int, double,
-                                            const double2*, hipStream_t);
-template hipError_t launch_cols_fwd<double, ACC_PLAIN>(int, int, const ColJobs&, const double2*, hipStream_t);
-template hipError_t launch_cols_fwd<float, ACC_PLAIN>(int, int, const ColJobs&, const float2*, hipStream_t);
-template hipError_t launch_cols_fwd<float, ACC_TWOSUM>(int, int, const ColJobs&, const float2*, hipStream_t);
-template hipError_t launch_cols_fwd<float, ACC_WIDE>(int, int, const ColJobs&, const float2*, hipStream_t);
-template hipError_t launch_cols_tr<double>(int, int, const ColJobs&, const double2*, hipStream_t);
-template hipError_t launch_cols_tr<float>(int, int, const ColJobs&, const float2*, hipStream_t);
+template hipError_t launch_cols_spec<double>(int, const double2*, int, int, void*, int, double,
+                                             const double2*, int, int64_t, hipStream_t);
+template hipError_t launch_cols_spec<float>(int, const double2*, int, int, void*, int, double,
+                                            const double2*, int, int64_t, hipStream_t);
 
 }  // namespace bttbk

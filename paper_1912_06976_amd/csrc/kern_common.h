@@ -1,0 +1,88 @@
+// kern_common.h -- device helpers and launch utilities shared by the kernel
+// translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+
+#include "fft_core.h"
+#include "bttb_internal.h"
+
+namespace bttbk {
+
+// hardware block b -> logical block such that the blocks that the hardware
+// places on one XCD (b mod 8) get consecutive logical indices
+__device__ __forceinline__ int xcd_order(int b, int G)
+{
+    const int xcd = b & 7, k = b >> 3;
+    const int per = G >> 3, rem = G & 7;
+    return xcd < rem ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
+}
+
+// index of the job whose work range [begin, next begin) contains w
+template <typename JT> __device__ __forceinline__ int find_job(const JT& js, int w)
+{
+    int k = 0;
+    for (int i = 1; i < js.njobs; ++i)
+        if (w >= js.j[i].begin) k = i;
+    return k;
+}
+
+// minimum waves per SIMD requested for the column kernels (bounds the VGPRs
+// the compiler may use: 512 / waves)
+#ifndef BTTB_COL_WAVES
+#define BTTB_COL_WAVES 2
+#endif
+// CM: multiplier of the columns per block (a tuning choice, 1 or 2)
+template <int N, int CM = 1> struct ColCfg {
+    static constexpr int TPL = N / 8;
+    static constexpr int CPW = (TPL >= 256 ? 1 : 256 / TPL) * CM;   // columns per block
+    static constexpr int THREADS = CPW * TPL;
+};
+
+// a column tile of 2 is used only where its LDS fits in 160 KB
+template <typename T, int NN> constexpr bool col_tile2_fits()
+{
+    return (ColCfg<NN, 2>::CPW + 1) * lds_line_elems(NN) * (int)sizeof(cT<T>) <= 160 * 1024;
+}
+
+#define BTTB_LEN_SWITCH(n, MACRO) \
+    switch (n) {                  \
+    case 8: MACRO(8); break;      \
+    case 16: MACRO(16); break;    \
+    case 32: MACRO(32); break;    \
+    case 64: MACRO(64); break;    \
+    case 128: MACRO(128); break;  \
+    case 256: MACRO(256); break;  \
+    case 512: MACRO(512); break;  \
+    case 1024: MACRO(1024); break;\
+    case 2048: MACRO(2048); break;\
+    case 4096: MACRO(4096); break;\
+    default: return hipErrorInvalidValue; }
+
+// blocks of `kernel` that are resident on the whole current device at once
+// (occupancy per CU times the number of CUs); at least 1
+static inline int resident_blocks(const void* kernel, int threads)
+{
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) { (void)hipGetLastError(); return 256; }
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        ncu = 256;
+    }
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0);
+    if (e != hipSuccess || per < 1) {
+        // a failed query must not leave its error for the launch check
+        (void)hipGetLastError();
+        if (std::getenv("BTTB_DEBUG"))
+            std::fprintf(stderr, "bttb: occupancy query failed (%s, per=%d, threads=%d)\n", hipGetErrorString(e),
+                         per, threads);
+        per = 1;
+    }
+    return std::max(1, ncu * per);
+}
+
+}  // namespace bttbk

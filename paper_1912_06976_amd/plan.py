@@ -18,6 +18,8 @@ from ._lib import check
 
 _KIND = {"gravity": _lib.BTTB_GRAVITY_GZ, "magnetic": _lib.BTTB_MAGNETIC_TMI, "probe": _lib.BTTB_PROBE}
 _PREC = {"fp32": _lib.BTTB_FP32, "fp64": _lib.BTTB_FP64}
+_FORM = {"auto": _lib.BTTB_SPECTRUM_AUTO, "complex": _lib.BTTB_SPECTRUM_COMPLEX,
+         "real_even": _lib.BTTB_SPECTRUM_REAL_EVEN}
 _ACC = {"default": _lib.BTTB_ACC_DEFAULT, "plain": _lib.BTTB_ACC_PLAIN, "twosum": _lib.BTTB_ACC_TWOSUM,
         "wide": _lib.BTTB_ACC_WIDE}
 
@@ -50,7 +52,8 @@ def make_desc(problem: dict, precision: str = "fp32", accumulation: str = "defau
         field_nT=problem.get("field_nT", 50000.0), scale=problem.get("scale", 0.0),
         nx_fft=problem.get("nx_fft", 0), ny_fft=problem.get("ny_fft", 0),
         accumulation=_ACC[accumulation], layer_chunk=problem.get("layer_chunk", 0),
-        row_tile=problem.get("row_tile", 0), col_tile=problem.get("col_tile", 0))
+        row_tile=problem.get("row_tile", 0), col_tile=problem.get("col_tile", 0),
+        spectrum_form=_FORM[problem.get("spectrum_form", "auto")])
     return d, keep
 
 
@@ -75,6 +78,13 @@ def bttb_plan_query(plan: int, nrhs: int = 1):
                                                           ctypes.byref(wb), ctypes.byref(nx),
                                                           ctypes.byref(ny)))
     return sb.value, wb.value, nx.value, ny.value
+
+
+def bttb_plan_spectrum_form(plan: int) -> str:
+    """The plan's stored spectrum form: "complex" or "real_even"."""
+    f = ctypes.c_int32()
+    check("bttb_plan_spectrum_form", _lib.load().bttb_plan_spectrum_form(ctypes.c_void_p(plan), ctypes.byref(f)))
+    return {v: k for k, v in _FORM.items()}[f.value]
 
 
 def bttb_kernel_generate(plan: int, spectra: torch.Tensor, workspace: torch.Tensor, stream=None) -> None:
@@ -145,6 +155,7 @@ class Plan:
         self.device = torch.device(device)
         self.handle = bttb_plan_create(problem, precision, accumulation)
         self.spectra_bytes, self._ws1, self.nx_fft, self.ny_fft = bttb_plan_query(self.handle, 1)
+        self.spectrum_form = bttb_plan_spectrum_form(self.handle)
         self.sx, self.sy, self.nz = problem["sx"], problem["sy"], problem["nz"]
         self.nx = self.sx + problem.get("pxl", 0) + problem.get("pxr", 0)
         self.ny = self.sy + problem.get("pyl", 0) + problem.get("pyr", 0)

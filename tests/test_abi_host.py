@@ -58,7 +58,7 @@ def _create(prob, prec="fp32", **over):
     ("sx", 0, 1), ("sy", -3, 1), ("nz", 0, 1), ("pxl", -1, 1), ("dx", 0.0, 1), ("dy", float("nan"), 1),
     ("dz", -1.0, 1), ("station_height", -1.0, 1), ("problem", 7, 1), ("precision", 3, 1),
     ("nx", 17, 1), ("nx_fft", 16, 1), ("nx_fft", 96, 3), ("ny_fft", 8192, 3), ("accumulation", 9, 1),
-    ("layer_chunk", -1, 1), ("row_tile", 3, 1), ("col_tile", 4, 1),
+    ("layer_chunk", -1, 1), ("row_tile", 3, 1), ("col_tile", 4, 1), ("spectrum_form", 3, 1),
 ])
 def test_invalid_descriptors_rejected(lib, field, value, status):
     st, h, msg = _create(W.small_gravity(), **{field: value})
@@ -98,11 +98,19 @@ def test_null_pointers(lib):
 
 def test_sizes_and_fft_choice(lib):
     import paper_1912_06976_amd as B
-    h = B.bttb_plan_create(W.gravity_1024(), "fp32")
+    h = B.bttb_plan_create(dict(W.gravity_1024(), spectrum_form="complex"), "fp32")
     sb, wb, nx, ny = B.bttb_plan_query(h, 1)
     assert (nx, ny) == (2048, 2048)       # smallest power of two >= 1000 + 1024 - 1
     # spectra: 128 layers x 1024 packed columns x 2048 complex64, plus twiddle tables
     assert 128 * 2048 * 1024 * 8 <= sb <= 128 * 2048 * 1024 * 8 + 4 * 2048 * 16 + 4096
+    assert B.bttb_plan_spectrum_form(h) == "complex"
+    B.bttb_plan_destroy(h)
+    # real even form (default for gravity): 128 layers x 1025 lines x 1025
+    # FP32 values (line stride rounded up to 1056), plus twiddle tables
+    h = B.bttb_plan_create(W.gravity_1024(), "fp32")
+    sb, wb, nx, ny = B.bttb_plan_query(h, 1)
+    assert B.bttb_plan_spectrum_form(h) == "real_even"
+    assert 128 * 1025 * 1056 * 4 <= sb <= 128 * 1025 * 1056 * 4 + 4 * 2048 * 16 + 4096
     sb4, wb4, _, _ = B.bttb_plan_query(h, 4)
     assert sb4 == sb and wb4 > wb
     with pytest.raises(B.BttbError):
@@ -114,6 +122,30 @@ def test_sizes_and_fft_choice(lib):
     h = B.bttb_plan_create(dict(W.small_gravity(), nx_fft=64, ny_fft=128), "fp64")
     assert B.bttb_plan_query(h, 1)[2:] == (64, 128)
     B.bttb_plan_destroy(h)
+
+
+def test_spectrum_form_choice(lib):
+    import paper_1912_06976_amd as B
+    cases = [
+        (W.small_gravity(), "auto", "real_even"),
+        (W.magnetic_48x56(), "auto", "complex"),
+        (W.problem(W.PROBE, 3, 1, 1, dx=1.0, dy=1.0, dz=1.0), "auto", "complex"),
+        # equal paddings: 2 (s - 1 + p) + 1 = s + n - 1 always fits
+        (W.table1_problem(3, W.GRAVITY, True), "auto", "real_even"),
+        # s + n - 1 = 15 -> N = 16, but 2 (5 - 1 + 6) + 1 = 21 > 16
+        (W.problem(W.GRAVITY, 5, 5, 2, 6, 0, 0, 0, dx=10.0, dy=10.0, dz=5.0), "auto", "complex"),
+        # the same with room: N = 32
+        (W.problem(W.GRAVITY, 5, 5, 2, 6, 0, 0, 0, dx=10.0, dy=10.0, dz=5.0, nx_fft=32), "auto", "real_even"),
+        (W.small_gravity(), "complex", "complex"),
+    ]
+    for pr, req, got in cases:
+        h = B.bttb_plan_create(dict(pr, spectrum_form=req), "fp32")
+        assert B.bttb_plan_spectrum_form(h) == got, (pr, req)
+        B.bttb_plan_destroy(h)
+    for pr in (W.magnetic_48x56(), W.problem(W.GRAVITY, 5, 5, 2, 6, 0, 0, 0, dx=10.0, dy=10.0, dz=5.0)):
+        st, h, msg = _create(dict(pr, spectrum_form="real_even"))
+        assert st == 3 and h.value is None and "REAL_EVEN" in msg
+    assert lib.bttb_plan_spectrum_form(None, None) == 2
 
 
 def test_workspace_too_small_is_rejected_before_launch(lib):

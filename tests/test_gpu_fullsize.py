@@ -21,16 +21,16 @@ def torch_cuda():
     return torch
 
 
-def _run(torch, pr, m, r):
+def _run(torch, pr, m, r, variants=(("fp32", "auto"), ("fp64", "auto"))):
     from paper_1912_06976_amd import Plan
     out = {}
-    for prec in ("fp32", "fp64"):
-        plan = Plan(pr, prec).generate()
+    for prec, form in variants:
+        plan = Plan(dict(pr, spectrum_form=form), prec).generate()
         dt = plan.dtype
         d = plan.forward(torch.tensor(m, dtype=dt, device="cuda"))
         t = plan.transpose(torch.tensor(r, dtype=dt, device="cuda"))
         torch.cuda.synchronize()
-        out[prec] = (d.double().cpu().numpy(), t.double().cpu().numpy())
+        out[prec if form == "auto" else prec + "_" + form] = (d.double().cpu().numpy(), t.double().cpu().numpy())
         del plan, d, t
         torch.cuda.empty_cache()
     return out
@@ -46,18 +46,23 @@ def test_full_size_sampled(torch_cuda, name):
     pr = getattr(W, name)()
     nx, ny, nz = W.dims(pr)
     print("full size", name, flush=True)
+    variants = [("fp32", "auto"), ("fp64", "auto")]
     if name == "gravity_1024":
         m = W.ellipsoid_model(pr, 301)
         r = W.normal_data(pr, 302)
         nst, npr = 8, 32
+        # the default real even spectra and the complex ones
+        variants.append(("fp32", "complex"))
     else:
         m = W.box_model(pr, 501, nboxes=5)
         r = W.normal_data(pr, 502)
         nst, npr = 16, 48
-    out = _run(torch_cuda, pr, m, r)
+    out = _run(torch_cuda, pr, m, r, variants)
     # FP32 against FP64 over the whole vectors
-    assert _rel(out["fp32"][0], out["fp64"][0]) <= 2e-5
-    assert _rel(out["fp32"][1], out["fp64"][1]) <= 2e-5
+    for key in out:
+        if key.startswith("fp32"):
+            assert _rel(out[key][0], out["fp64"][0]) <= 2e-5, key
+            assert _rel(out[key][1], out["fp64"][1]) <= 2e-5, key
     # both against the oracle's direct sums at seeded stations / prisms,
     # including the corners of the station grid and the padded edges
     P = oracle_problem(pr)
@@ -71,7 +76,8 @@ def test_full_size_sampled(torch_cuda, name):
     # FP64: both sides evaluate the closed-form corner sums in double; for
     # prisms ~1000 cells away they cancel to ~1e-6 relative per entry, which
     # bounds the agreement of the two at the 1e-9 level (not 1e-12)
-    for prec, tol in (("fp32", 2e-5), ("fp64", 1e-8)):
+    for prec in out:
+        tol = 1e-8 if prec == "fp64" else 2e-5
         d, t = out[prec]
         gd = np.array([d[j, i] for (i, j) in st])
         gt = np.array([t[rr, q, p] for (p, q, rr) in pq])

@@ -102,7 +102,10 @@ def test_paper_circulant_example(torch_cuda):
     assert np.all(col[3:-2] == 0)
 
 
-@pytest.mark.parametrize("pr", [W.small_gravity(), W.magnetic_48x56(),
+@pytest.mark.parametrize("pr", [W.small_gravity(), dict(W.small_gravity(), spectrum_form="complex"),
+                                W.problem(W.GRAVITY, 10, 7, 2, 2, 5, 1, 0, dx=30.0, dy=30.0, dz=15.0, h=3.0,
+                                          nx_fft=64, ny_fft=32),
+                                W.magnetic_48x56(),
                                 W.problem(W.MAGNETIC, 9, 6, 3, 1, 2, 2, 1, dx=50.0, dy=100.0, dz=30.0,
                                           h=7.0, incl=-30.0, decl=140.0, field_nT=52000.0)])
 def test_generator_entries_match_quad_oracle(torch_cuda, orc, pr):
@@ -115,15 +118,30 @@ def test_generator_entries_match_quad_oracle(torch_cuda, orc, pr):
     eps = np.finfo(float).eps
     for r in range(P.nz):
         T = plan.debug_generator(r)
-        # T[ay mod Ny][ax mod Nx] = h(-ax - pxl, -ay - pyl) for ax in [-(nx-1), sx-1]
-        ax = np.arange(-(P.nx - 1), P.sx)
-        ay = np.arange(-(P.ny - 1), P.sy)
+        if plan.spectrum_form == "complex":
+            # T[ay mod Ny][ax mod Nx] = h(-ax - pxl, -ay - pyl) for ax in [-(nx-1), sx-1]
+            ax = np.arange(-(P.nx - 1), P.sx)
+            ay = np.arange(-(P.ny - 1), P.sy)
+            ox = -ax - P.pxl
+            oy = -ay - P.pyl
+        else:
+            # centred even placement: T[ay mod Ny][ax mod Nx] = h(|ax|, |ay|) for
+            # |ax| <= sx - 1 + max(pxl, pxr) (h is even: take the offset sign
+            # the oracle's table covers)
+            bx, by = P.sx - 1 + max(P.pxl, P.pxr), P.sy - 1 + max(P.pyl, P.pyr)
+            ax = np.arange(-bx, bx + 1)
+            ay = np.arange(-by, by + 1)
+            ox = np.where(np.abs(ax) <= P.nx - 1 - P.pxl, np.abs(ax), -np.abs(ax))
+            oy = np.where(np.abs(ay) <= P.ny - 1 - P.pyl, np.abs(ay), -np.abs(ay))
         got = T[np.ix_(ay % Ny, ax % Nx)]
-        ox = -ax - P.pxl + (P.sx - 1 + P.pxl)
-        oy = -ay - P.pyl + (P.sy - 1 + P.pyl)
-        ref = t[r][np.ix_(oy, ox)]
-        bound = 32 * eps * a[r][np.ix_(oy, ox)] + 1e-300
+        ix = ox + (P.sx - 1 + P.pxl)
+        iy = oy + (P.sy - 1 + P.pyl)
+        ref = t[r][np.ix_(iy, ix)]
+        bound = 32 * eps * a[r][np.ix_(iy, ix)] + 1e-300
         assert np.all(np.abs(got - ref) <= bound), np.max(np.abs(got - ref) / bound)
+        rest = np.ones((Ny, Nx), dtype=bool)
+        rest[np.ix_(ay % Ny, ax % Nx)] = False
+        assert np.all(T[rest] == 0.0)
 
 
 # ---------------------------------------------------------------------------
@@ -140,9 +158,10 @@ def _products(torch, plan, m, v):
     return d.double().cpu().numpy(), t.double().cpu().numpy()
 
 
-def test_small_gravity_fp64(torch_cuda, orc):
-    pr = W.small_gravity()
-    _say("small gravity fp64")
+@pytest.mark.parametrize("form", ["auto", "complex"])
+def test_small_gravity_fp64(torch_cuda, orc, form):
+    pr = dict(W.small_gravity(), spectrum_form=form)
+    _say("small gravity fp64", form)
     P, G = _dense_ref(orc, pr)
     m = W.uniform_model(pr, 101)
     v = W.normal_data(pr, 102)
@@ -194,9 +213,12 @@ EDGE = [
 @pytest.mark.parametrize("k", range(len(EDGE)))
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("row_tile", [4, 8])
-def test_edge_shapes(torch_cuda, orc, k, prec, row_tile):
-    pr = dict(EDGE[k], row_tile=row_tile)
-    _say("edge shape", k, prec)
+@pytest.mark.parametrize("form", ["auto", "complex"])
+def test_edge_shapes(torch_cuda, orc, k, prec, row_tile, form):
+    if form == "complex" and EDGE[k]["kind"] != W.GRAVITY:
+        pytest.skip("the complex form is the only one for this kernel (covered by 'auto')")
+    pr = dict(EDGE[k], row_tile=row_tile, spectrum_form=form)
+    _say("edge shape", k, prec, row_tile, form)
     P, G = _dense_ref(orc, pr)
     m = W.normal_model(pr, 1000 + k)
     v = W.normal_data(pr, 2000 + k)
@@ -204,6 +226,23 @@ def test_edge_shapes(torch_cuda, orc, k, prec, row_tile):
     tol = TOL64 if prec == "fp64" else TOL32
     assert rel_l2(d.ravel(), G @ m.ravel()) <= tol
     assert rel_l2(t.ravel(), G.T @ v.ravel()) <= tol
+
+
+@pytest.mark.parametrize("acc", ["default", "plain", "twosum", "wide"])
+@pytest.mark.parametrize("form", ["auto", "complex"])
+def test_gravity_fp32_odd_padding(torch_cuda, orc, acc, form):
+    # odd left padding in x and y (phase sign at the Nyquist column), a
+    # uniform model as in the paper's gravity experiments
+    pr = dict(W.problem(W.GRAVITY, 23, 17, 6, 3, 2, 5, 4, dx=40.0, dy=25.0, dz=20.0, h=5.0), spectrum_form=form)
+    _say("gravity fp32 odd padding", acc, form)
+    P, G = _dense_ref(orc, pr)
+    m = W.uniform_model(pr, 121)
+    v = W.normal_data(pr, 122)
+    plan = _plan(pr, "fp32", acc)
+    assert plan.spectrum_form == ("real_even" if form == "auto" else "complex")
+    d, t = _products(torch_cuda, plan, m, v)
+    assert rel_l2(d.ravel(), G @ m.ravel()) <= TOL32
+    assert rel_l2(t.ravel(), G.T @ v.ravel()) <= TOL32
 
 
 @pytest.mark.parametrize("k", [1, 2, 3, 4])
