@@ -101,6 +101,10 @@ template <int N> __device__ __forceinline__ int mirror_idx(int t, int m) {
     return lpad((N - t - m * (N / 8)) & (N - 1));
 }
 
+// minimum waves per SIMD of the column kernels: FP64 keeps its twiddles (80
+// VGPRs) and the prefetch buffers in registers only with the full 512 VGPRs
+template <typename T> constexpr int col_waves() { return sizeof(T) == 8 ? 1 : BTTB_COL_WAVES; }
+
 // Real even form: position k = t + m TPL of a line reads the stored value at
 // min(k, N - k), i.e. t + m TPL for m < 4 and (8 - m) TPL - t for m >= 4
 // (m = 4, t = 0 is the Nyquist bin N/2).  Consecutive threads read
@@ -142,7 +146,7 @@ __device__ __forceinline__ void load_real_even(cT<T> (&tn)[8], const ColJob& J, 
 // X[((q * nz + r) * ncols + kx) * lda + y], y < na = ny (packed row-pass
 // output), nl = nz layers; b = Y with Y[(q * ncols + kx) * ldb + y], y < nb = sy.
 template <typename T, int N, int NR, int ACC, int CM, int SF>
-__global__ void __launch_bounds__((ColCfg<N, CM>::THREADS), BTTB_COL_WAVES)
+__global__ void __launch_bounds__((ColCfg<N, CM>::THREADS), (col_waves<T>()))
 k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
 {
     using C = ColCfg<N, CM>;
@@ -195,8 +199,10 @@ k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
             }
         }
     };
-    load_layer(0);
+    constexpr bool PIPE = true;
+    if (PIPE) load_layer(0);
     for (int r = 0; r < nz; ++r) {
+        if (!PIPE) load_layer(r);
         cT<T> tv[8], v[NR][8];
 #pragma unroll
         for (int m = 0; m < 8; ++m) tv[m] = tn[m];
@@ -204,7 +210,7 @@ k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
         for (int q = 0; q < NR; ++q)
 #pragma unroll
             for (int m = 0; m < 8; ++m) v[q][m] = xn[q][m];
-        if (r + 1 < nz) load_layer(r + 1);
+        if (PIPE && r + 1 < nz) load_layer(r + 1);
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
             if (zhi) fft_line<T, N, -1, true>(v[q], xl, twl, t);
@@ -283,7 +289,7 @@ k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
 // block (at most a few times), so every block gets the same number of layers
 // whatever the number of resident blocks.
 template <typename T, int N, int NR, int CM, int SF>
-__global__ void __launch_bounds__((ColCfg<N, CM>::THREADS), BTTB_COL_WAVES)
+__global__ void __launch_bounds__((ColCfg<N, CM>::THREADS), (col_waves<T>()))
 k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
 {
     using C = ColCfg<N, CM>;
@@ -322,8 +328,10 @@ k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
     };
     int cur_k = -1, cur_key = -1;
     cT<T> rh[8];
-    if (u0 < u1) load_spec(u0);
+    constexpr bool PIPE = true;
+    if (PIPE && u0 < u1) load_spec(u0);
     for (int u = u0; u < u1; ++u) {
+        if (!PIPE) load_spec(u);
         int k, key, l;
         decode(u, k, key, l);
         const ColJob& J = jobs.j[k];
@@ -335,7 +343,7 @@ k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
         cT<T> tv[8];
 #pragma unroll
         for (int m = 0; m < 8; ++m) tv[m] = tn[m];
-        if (u + 1 < u1) load_spec(u + 1);
+        if (PIPE && u + 1 < u1) load_spec(u + 1);
         if (k != cur_k || key != cur_key) {
             // R^ of this column: FFT_y of the packed row-pass output of the data
             const cT<T>* rs = (const cT<T>*)J.a + ((int64_t)q * J.ncols + (ok ? col : 0)) * J.lda;
