@@ -140,6 +140,13 @@ __global__ void k_generate(GenParams P, int r0, double* __restrict__ out)
 // ---------------------------------------------------------------------------
 // row transforms
 // ---------------------------------------------------------------------------
+// two adjacent complex values with one 16-byte (FP32) store; the address
+// must be 16-byte aligned (FP64: two 16-byte stores)
+template <typename T> __device__ __forceinline__ void store_pair(cT<T>* o, cT<T> a, cT<T> b)
+{
+    if constexpr (sizeof(T) == 4) *(float4*)o = make_float4(a.x, a.y, b.x, b.y);
+    else { o[0] = a; o[1] = b; }
+}
 // P0: pairs of rows per block for long rows (a tuning choice, 2 or 4)
 template <typename T, int N, int P0 = 4> struct RowCfg {
     static constexpr int TPL = N / 8;
@@ -154,6 +161,11 @@ template <typename T, int N, int P0 = 4> struct RowCfg {
     static constexpr int XCH = PAIRS * lds_line_elems(N);
     static constexpr int LDS = STAGE > XCH ? STAGE : XCH;
     static constexpr int TWO = LDS;                 // offset of the LDS twiddle table
+    // r2c: the complex transforms Z of the PAIRS row pairs staged by
+    // frequency, [k][pair] with a padded row (bank spread of the writes)
+    static constexpr int ZROW = PAIRS > 1 ? PAIRS + 1 : 1;
+    static constexpr int ZSTAGE = N * ZROW;
+    static constexpr int LDS_R2C = ZSTAGE > XCH ? ZSTAGE : XCH;
 };
 
 // Row kernels are persistent: gridDim.x blocks (about the number that fit on
@@ -174,12 +186,12 @@ k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
 {
     using C = RowCfg<T, N, P0>;
     constexpr int TPL = C::TPL;
-    __shared__ cT<T> lds[C::LDS + TableTwiddles<T, N>::size()];
+    __shared__ cT<T> lds[C::LDS_R2C + TableTwiddles<T, N>::size()];
     const int G = gridDim.x, total = jobs.total;
     const int pr = threadIdx.x / TPL, t = threadIdx.x % TPL;
-    TableTwiddles<T, N>::build(lds + C::TWO, tw, threadIdx.x, C::THREADS);
+    TableTwiddles<T, N>::build(lds + C::LDS_R2C, tw, threadIdx.x, C::THREADS);
     __syncthreads();
-    const TableTwiddles<T, N> twl{lds + C::TWO};
+    const TableTwiddles<T, N> twl{lds + C::LDS_R2C};
     cT<T>* xl = lds + pr * lds_line_elems(N);
     auto load = [&](int g, cT<T> (&v)[8]) {
         const RowJob& J = jobs.j[find_job(jobs, g)];
@@ -210,41 +222,39 @@ k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
         const int row0 = (gl % J.bpb) * C::RT;
         if (J.nv <= N / 2) fft_line<T, N, -1, true>(v, xl, twl, t);
         else fft_line<T, N, -1, false>(v, xl, twl, t);
-        // split Z = FFT(a + i c) into A = FFT(a), C = FFT(c):
-        // A[k] = (Z[k] + conj Z[N-k]) / 2, C[k] = (Z[k] - conj Z[N-k]) / (2 i)
+        // stage Z = FFT(a + i c) of every pair by frequency
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < 8; ++m) xl[lpad(t + m * TPL)] = v[m];
+        for (int m = 0; m < 8; ++m) lds[(t + m * TPL) * C::ZROW + pr] = v[m];
         __syncthreads();
-        cT<T> A[5], Cc[5];
-#pragma unroll
-        for (int m = 0; m < 5; ++m) {
-            const int k = t + m * TPL;
-            if (m < 4 || t == 0) {
-                const cT<T> z = v[m];
-                const cT<T> zr = xl[lpad((N - k) & (N - 1))];
-                A[m] = mk<T>((T)0.5 * (z.x + zr.x), (T)0.5 * (z.y - zr.y));
-                Cc[m] = mk<T>((T)0.5 * (z.y + zr.y), (T)0.5 * (zr.x - z.x));
-            }
-        }
-        if (t == 0) {   // pack the real bins 0 and N/2 into slot 0
-            A[0] = mk<T>(A[0].x, A[4].x);
-            Cc[0] = mk<T>(Cc[0].x, Cc[4].x);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int k = t + m * TPL;
-            lds[k * C::SROW + 2 * pr] = A[m];
-            lds[k * C::SROW + 2 * pr + 1] = Cc[m];
-        }
-        __syncthreads();
+        // element (kx, pair): split Z into the two rows' half spectra,
+        //   A[k] = (Z[k] + conj Z[N-k]) / 2,  C[k] = (Z[k] - conj Z[N-k]) / (2 i),
+        // slot 0 packing the real bins 0 and N/2, and store both rows
+        // (adjacent in the column) with one 2-element store
         cT<T>* dst = (cT<T>*)J.out + (int64_t)b * J.out_bs;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int e = threadIdx.x + i * C::THREADS;   // HALF * RT = 8 * THREADS
-            const int kx = e / C::RT, rr = e % C::RT;
-            if (row0 + rr < J.nrows) dst[(int64_t)kx * J.out_ld + row0 + rr] = lds[kx * C::SROW + rr];
+        for (int i = 0; i < (C::HALF * C::PAIRS) / C::THREADS; ++i) {
+            const int e = threadIdx.x + i * C::THREADS;
+            const int kx = e / C::PAIRS, q = e % C::PAIRS;
+            const cT<T> z = lds[kx * C::ZROW + q];
+            const cT<T> zr = lds[((N - kx) & (N - 1)) * C::ZROW + q];
+            cT<T> A, Cc;
+            if (kx == 0) {
+                const cT<T> zh = lds[(N / 2) * C::ZROW + q];
+                A = mk<T>(z.x, zh.x);
+                Cc = mk<T>(z.y, zh.y);
+            } else {
+                A = mk<T>((T)0.5 * (z.x + zr.x), (T)0.5 * (z.y - zr.y));
+                Cc = mk<T>((T)0.5 * (z.y + zr.y), (T)0.5 * (zr.x - z.x));
+            }
+            const int ra = row0 + 2 * q;
+            cT<T>* o = dst + (int64_t)kx * J.out_ld + ra;
+            if (ra + 1 < J.nrows && ((uintptr_t)o & 15) == 0) {
+                store_pair<T>(o, A, Cc);
+            } else {
+                if (ra < J.nrows) o[0] = A;
+                if (ra + 1 < J.nrows) o[1] = Cc;
+            }
         }
 #pragma unroll
         for (int m = 0; m < 8; ++m) v[m] = vn[m];
@@ -270,6 +280,8 @@ k_rows_c2r(RowJobs jobs, const cT<T>* __restrict__ tw)
     cT<T>* xl = lds + pr * lds_line_elems(N);
     // tile of the packed half spectra of RT rows: HALF * RT = 8 * THREADS
     // elements, element e = threadIdx.x + i THREADS at (kx, row) = (e / RT, e % RT)
+    // (8-byte loads: eight lanes per 64-byte column segment; 16-byte loads,
+    // with twice the segments per instruction, measured slower)
     auto load = [&](int g, cT<T> (&tl)[8]) {
         const RowJob& J = jobs.j[find_job(jobs, g)];
         const int gl = g - J.begin;
