@@ -102,8 +102,14 @@ template <int N> __device__ __forceinline__ int mirror_idx(int t, int m) {
 }
 
 // minimum waves per SIMD of the column kernels: FP64 keeps its twiddles (80
-// VGPRs) and the prefetch buffers in registers only with the full 512 VGPRs
+// VGPRs) and the prefetch buffers in registers only with the full 512 VGPRs;
+// the FP32 transpose kernel fits three waves (168 VGPRs) without spills at
+// N = 2048 with one column per block (other shapes would spill)
 template <typename T> constexpr int col_waves() { return sizeof(T) == 8 ? 1 : BTTB_COL_WAVES; }
+template <typename T, int N, int CM> constexpr int col_waves_tr()
+{
+    return sizeof(T) == 8 ? 1 : (N == 2048 && CM == 1 ? 3 : BTTB_COL_WAVES);
+}
 
 // Real even form: position k = t + m TPL of a line reads the stored value at
 // min(k, N - k), i.e. t + m TPL for m < 4 and (8 - m) TPL - t for m >= 4
@@ -289,7 +295,7 @@ k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
 // block (at most a few times), so every block gets the same number of layers
 // whatever the number of resident blocks.
 template <typename T, int N, int NR, int CM, int SF>
-__global__ void __launch_bounds__((ColCfg<N, CM>::THREADS), (col_waves<T>()))
+__global__ void __launch_bounds__((ColCfg<N, CM>::THREADS), (col_waves_tr<T, N, CM>()))
 k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
 {
     using C = ColCfg<N, CM>;

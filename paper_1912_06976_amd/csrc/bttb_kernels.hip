@@ -163,9 +163,11 @@ template <typename T, int N, int P0 = 4> struct RowCfg {
     static constexpr int TWO = LDS;                 // offset of the LDS twiddle table
     // r2c: the complex transforms Z of the PAIRS row pairs staged by
     // frequency, [k][pair] with a padded row (bank spread of the writes)
+    // (FP32 only; FP64 splits through the line buffers and stages the half
+    // spectra [kx][row] like the c2r tile, which measured faster there)
     static constexpr int ZROW = PAIRS > 1 ? PAIRS + 1 : 1;
     static constexpr int ZSTAGE = N * ZROW;
-    static constexpr int LDS_R2C = ZSTAGE > XCH ? ZSTAGE : XCH;
+    static constexpr int LDS_R2C = sizeof(T) == 4 ? (ZSTAGE > XCH ? ZSTAGE : XCH) : LDS;
 };
 
 // Row kernels are persistent: gridDim.x blocks (about the number that fit on
@@ -222,38 +224,76 @@ k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
         const int row0 = (gl % J.bpb) * C::RT;
         if (J.nv <= N / 2) fft_line<T, N, -1, true>(v, xl, twl, t);
         else fft_line<T, N, -1, false>(v, xl, twl, t);
-        // stage Z = FFT(a + i c) of every pair by frequency
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < 8; ++m) lds[(t + m * TPL) * C::ZROW + pr] = v[m];
-        __syncthreads();
-        // element (kx, pair): split Z into the two rows' half spectra,
-        //   A[k] = (Z[k] + conj Z[N-k]) / 2,  C[k] = (Z[k] - conj Z[N-k]) / (2 i),
-        // slot 0 packing the real bins 0 and N/2, and store both rows
-        // (adjacent in the column) with one 2-element store
         cT<T>* dst = (cT<T>*)J.out + (int64_t)b * J.out_bs;
+        if constexpr (sizeof(T) == 4) {
+            // stage Z = FFT(a + i c) of every pair by frequency, then split it
+            // into the two rows' half spectra while the tile is stored:
+            //   A[k] = (Z[k] + conj Z[N-k]) / 2,  C[k] = (Z[k] - conj Z[N-k]) / (2 i),
+            // slot 0 packing the real bins 0 and N/2; element (kx, pair) stores
+            // both rows (adjacent in the column) with one 16-byte store
+            __syncthreads();
 #pragma unroll
-        for (int i = 0; i < (C::HALF * C::PAIRS) / C::THREADS; ++i) {
-            const int e = threadIdx.x + i * C::THREADS;
-            const int kx = e / C::PAIRS, q = e % C::PAIRS;
-            const cT<T> z = lds[kx * C::ZROW + q];
-            const cT<T> zr = lds[((N - kx) & (N - 1)) * C::ZROW + q];
-            cT<T> A, Cc;
-            if (kx == 0) {
-                const cT<T> zh = lds[(N / 2) * C::ZROW + q];
-                A = mk<T>(z.x, zh.x);
-                Cc = mk<T>(z.y, zh.y);
-            } else {
-                A = mk<T>((T)0.5 * (z.x + zr.x), (T)0.5 * (z.y - zr.y));
-                Cc = mk<T>((T)0.5 * (z.y + zr.y), (T)0.5 * (zr.x - z.x));
+            for (int m = 0; m < 8; ++m) lds[(t + m * TPL) * C::ZROW + pr] = v[m];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < (C::HALF * C::PAIRS) / C::THREADS; ++i) {
+                const int e = threadIdx.x + i * C::THREADS;
+                const int kx = e / C::PAIRS, q = e % C::PAIRS;
+                const cT<T> z = lds[kx * C::ZROW + q];
+                cT<T> A, Cc;
+                if (kx == 0) {
+                    const cT<T> zh = lds[(N / 2) * C::ZROW + q];
+                    A = mk<T>(z.x, zh.x);
+                    Cc = mk<T>(z.y, zh.y);
+                } else {
+                    const cT<T> zr = lds[(N - kx) * C::ZROW + q];
+                    A = mk<T>((T)0.5 * (z.x + zr.x), (T)0.5 * (z.y - zr.y));
+                    Cc = mk<T>((T)0.5 * (z.y + zr.y), (T)0.5 * (zr.x - z.x));
+                }
+                const int ra = row0 + 2 * q;
+                cT<T>* o = dst + (int64_t)kx * J.out_ld + ra;
+                if (ra + 1 < J.nrows && ((uintptr_t)o & 15) == 0) {
+                    store_pair<T>(o, A, Cc);
+                } else {
+                    if (ra < J.nrows) o[0] = A;
+                    if (ra + 1 < J.nrows) o[1] = Cc;
+                }
             }
-            const int ra = row0 + 2 * q;
-            cT<T>* o = dst + (int64_t)kx * J.out_ld + ra;
-            if (ra + 1 < J.nrows && ((uintptr_t)o & 15) == 0) {
-                store_pair<T>(o, A, Cc);
-            } else {
-                if (ra < J.nrows) o[0] = A;
-                if (ra + 1 < J.nrows) o[1] = Cc;
+        } else {
+            // split through the line buffer (mirror reads), then stage the
+            // half spectra [kx][row] and store the tile
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < 8; ++m) xl[lpad(t + m * TPL)] = v[m];
+            __syncthreads();
+            cT<T> A[5], Cc[5];
+#pragma unroll
+            for (int m = 0; m < 5; ++m) {
+                const int k = t + m * TPL;
+                if (m < 4 || t == 0) {
+                    const cT<T> z = v[m];
+                    const cT<T> zr = xl[lpad((N - k) & (N - 1))];
+                    A[m] = mk<T>((T)0.5 * (z.x + zr.x), (T)0.5 * (z.y - zr.y));
+                    Cc[m] = mk<T>((T)0.5 * (z.y + zr.y), (T)0.5 * (zr.x - z.x));
+                }
+            }
+            if (t == 0) {   // pack the real bins 0 and N/2 into slot 0
+                A[0] = mk<T>(A[0].x, A[4].x);
+                Cc[0] = mk<T>(Cc[0].x, Cc[4].x);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int k = t + m * TPL;
+                lds[k * C::SROW + 2 * pr] = A[m];
+                lds[k * C::SROW + 2 * pr + 1] = Cc[m];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int e = threadIdx.x + i * C::THREADS;   // HALF * RT = 8 * THREADS
+                const int kx = e / C::RT, rr = e % C::RT;
+                if (row0 + rr < J.nrows) dst[(int64_t)kx * J.out_ld + row0 + rr] = lds[kx * C::SROW + rr];
             }
         }
 #pragma unroll

@@ -41,13 +41,14 @@ template <typename T, int DIR> __device__ __forceinline__ cT<T> mul_i(cT<T> a) {
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n >> 1); }
 
-// padded LDS index: one pad element after every 2^BTTB_LPAD_SHIFT spreads the
-// strided Stockham writes over the banks
-#ifndef BTTB_LPAD_SHIFT
-#define BTTB_LPAD_SHIFT 5
-#endif
-__device__ __forceinline__ int lpad(int x) { return x + (x >> BTTB_LPAD_SHIFT); }
-constexpr int lds_line_elems(int n) { return n + (n >> BTTB_LPAD_SHIFT); }
+// LDS index of position x of a line buffer: the low five bits XORed with
+// bits 3..7, a permutation within each aligned block of 32 elements that
+// spreads the strided Stockham writes and the contiguous reads of fft_line
+// over the LDS banks (no conflicts for N >= 64 with 8- or 16-byte elements).
+// Line buffers of one block are lds_line_elems(n) elements apart; the small
+// offset spreads the lines that share a wave.
+__device__ __forceinline__ int lpad(int x) { return x ^ ((x >> 3) & 31); }
+constexpr int lds_line_elems(int n) { return n + (n >= 64 ? 8 : 4); }
 
 template <int N> struct FftShape {
     static constexpr int LOG = ilog2(N);
