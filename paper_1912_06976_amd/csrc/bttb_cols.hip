@@ -148,9 +148,10 @@ __device__ __forceinline__ void load_real_even(cT<T> (&tn)[8], const ColJob& J, 
 }
 
 // Forward column pass over every job of the table (one block per CPW
-// columns of one right-hand-side block of one job).  Job: a = X with
-// X[((q * nz + r) * ncols + kx) * lda + y], y < na = ny (packed row-pass
-// output), nl = nz layers; b = Y with Y[(q * ncols + kx) * ldb + y], y < nb = sy.
+// columns of one right-hand-side block of one job).  Job: a = X, the packed
+// row-pass output in panels, block (q, r) at X + (q * nz + r) * ncols * lda,
+// y < na = ny, nl = nz layers; b = Y, block q at Y + q * ncols * ldb,
+// y < nb = sy.
 template <typename T, int N, int NR, int ACC, int CM, int SF>
 __global__ void __launch_bounds__((ColCfg<N, CM>::THREADS), (col_waves<T>()))
 k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
@@ -197,11 +198,11 @@ k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
             const int qq = q0 + q;
-            const cT<T>* xs = X + (((int64_t)(qq < nrhs ? qq : 0) * nz + r) * ncols + ccol) * ldx;
+            const cT<T>* xs = X + ((int64_t)(qq < nrhs ? qq : 0) * nz + r) * ncols * ldx;
 #pragma unroll
             for (int m = 0; m < 8; ++m) {
                 const int y = t + m * TPL;
-                xn[q][m] = (ok && qq < nrhs && y < ny) ? xs[y] : mk<T>(0, 0);
+                xn[q][m] = (ok && qq < nrhs && y < ny) ? xs[pidx(ccol, y, ncols)] : mk<T>(0, 0);
             }
         }
     };
@@ -274,20 +275,20 @@ k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
         }
         fft_line<T, N, +1, false>(w, xl, twl, t);
         if (ok && qq < nrhs) {
-            cT<T>* ys = Y + ((int64_t)qq * ncols + col) * ldy;
+            cT<T>* ys = Y + (int64_t)qq * ncols * ldy;
 #pragma unroll
             for (int m = 0; m < 8; ++m) {
                 const int y = t + m * TPL;
-                if (y < sy) ys[y] = w[m];
+                if (y < sy) ys[pidx(col, y, ncols)] = w[m];
             }
         }
     }
 }
 
 // Transpose column pass over every job of the table, layers [r0, r0 + nl).
-// Job: a = R with R[(q * ncols + kx) * lda + y], y < na = sy (packed row-pass
-// output of the data); b = Z with Z[((q * nl + r - r0) * ncols + kx) * ldb + y],
-// y < nb = ny.
+// Job: a = R, the packed row-pass output of the data in panels, block q at
+// R + q * ncols * lda, y < na = sy; b = Z, block (q, r - r0) at
+// Z + (q * nl + r - r0) * ncols * ldb, y < nb = ny.
 // The kernel is persistent and balanced: the work of all jobs is the list of
 // units (job, right-hand side q, column block cb, layer l), layer fastest,
 // and block w processes the contiguous range [w U / G, (w + 1) U / G).  A
@@ -352,11 +353,11 @@ k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
         if (PIPE && u + 1 < u1) load_spec(u + 1);
         if (k != cur_k || key != cur_key) {
             // R^ of this column: FFT_y of the packed row-pass output of the data
-            const cT<T>* rs = (const cT<T>*)J.a + ((int64_t)q * J.ncols + (ok ? col : 0)) * J.lda;
+            const cT<T>* rs = (const cT<T>*)J.a + (int64_t)q * J.ncols * J.lda;
 #pragma unroll
             for (int m = 0; m < 8; ++m) {
                 const int y = t + m * TPL;
-                rh[m] = (ok && y < J.na) ? rs[y] : mk<T>(0, 0);
+                rh[m] = (ok && y < J.na) ? rs[pidx(col, y, J.ncols)] : mk<T>(0, 0);
             }
             if (J.na <= N / 2) fft_line<T, N, -1, true>(rh, xl, twl, t);
             else fft_line<T, N, -1, false>(rh, xl, twl, t);
@@ -421,11 +422,11 @@ k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
         }
         fft_line<T, N, +1, false>(v, xl, twl, t);
         if (ok) {
-            cT<T>* zs = (cT<T>*)J.b + (((int64_t)q * J.nl + l) * J.ncols + col) * J.ldb;
+            cT<T>* zs = (cT<T>*)J.b + ((int64_t)q * J.nl + l) * J.ncols * J.ldb;
 #pragma unroll
             for (int m = 0; m < 8; ++m) {
                 const int y = t + m * TPL;
-                if (y < J.nb) zs[y] = v[m];
+                if (y < J.nb) zs[pidx(col, y, J.ncols)] = v[m];
             }
         }
     }

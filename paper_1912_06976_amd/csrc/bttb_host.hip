@@ -209,12 +209,14 @@ WsLayout ws_layout(const bttb_plan_s* P, int nrhs)
     L.gen_a = 0;
     L.gen_b = align_up((size_t)P->gen_batch * P->Nx * (size_t)P->Ny * 8);
     L.gen_total = align_up(L.gen_b + (size_t)P->gen_batch * P->ncols * (size_t)P->Ny * 16);
+    // half spectra in panels: ncols * panel_rows(rows) per block
+    const size_t pny = (size_t)panel_rows(P->ny), psy = (size_t)panel_rows(P->sy);
     L.fwd_x = 0;
-    L.fwd_y = align_up((size_t)nrhs * P->nz * P->ncols * (size_t)P->ny * csz);
-    L.fwd_total = align_up(L.fwd_y + (size_t)nrhs * P->ncols * (size_t)P->sy * csz);
+    L.fwd_y = align_up((size_t)nrhs * P->nz * P->ncols * pny * csz);
+    L.fwd_total = align_up(L.fwd_y + (size_t)nrhs * P->ncols * psy * csz);
     L.tr_r = 0;
-    L.tr_z = align_up((size_t)nrhs * P->ncols * (size_t)P->sy * csz);
-    L.tr_total = align_up(L.tr_z + (size_t)nrhs * P->tr_chunk * P->ncols * (size_t)P->ny * csz);
+    L.tr_z = align_up((size_t)nrhs * P->ncols * psy * csz);
+    L.tr_total = align_up(L.tr_z + (size_t)nrhs * P->tr_chunk * P->ncols * pny * csz);
     L.total = std::max({L.gen_total, L.fwd_total, L.tr_total});
     return L;
 }
@@ -265,7 +267,7 @@ bttb_status run_generate(const bttb_plan_s* P, char* spec, char* ws, hipStream_t
         if ((st = hip_check(launch_generate(g, r0, nl, g64, s), "generate")) != BTTB_OK) return st;
         RowJobs rj{};
         rj.njobs = 1;
-        rj.j[0] = RowJob{g64, w64, (int64_t)P->Nx * P->Ny, P->Nx, (int64_t)P->ncols * P->Ny, P->Ny,
+        rj.j[0] = RowJob{g64, w64, (int64_t)P->Nx * P->Ny, P->Nx, (int64_t)P->ncols * P->Ny, 0,
                          P->Nx, P->Ny, 0, 0};
         const int rt = row_group_rows<double>(P->Nx, 4);
         rj.j[0].bpb = (P->Ny + rt - 1) / rt;
@@ -451,13 +453,14 @@ bttb_status run_forward(const std::vector<Item>& items, hipStream_t s, hipEvent_
         const WsLayout L = ws_layout(P, it.nrhs);
         cT<T>* X = (cT<T>*)(it.ws + L.fwd_x);
         cT<T>* Y = (cT<T>*)(it.ws + L.fwd_y);
+        const int64_t pny = panel_rows(P->ny), psy = panel_rows(P->sy);
         r1.add(P->Nx, P->row_tile, tw_x<T>(P, it.spec),
-               RowJob{it.in, X, (int64_t)P->nx * P->ny, P->nx, (int64_t)P->ncols * P->ny, P->ny, P->nx, P->ny, 0, 0},
+               RowJob{it.in, X, (int64_t)P->nx * P->ny, P->nx, P->ncols * pny, 0, P->nx, P->ny, 0, 0},
                it.nrhs * P->nz);
         c2.add(ColKey{P->Ny, P->acc, P->col_tile, P->form}, tw_y<T>(P, it.spec),
-               col_job(P, X, it.spec, Y, P->ny, P->sy, P->ny, P->sy, 0, P->nz, it.nrhs));
+               col_job(P, X, it.spec, Y, pny, psy, P->ny, P->sy, 0, P->nz, it.nrhs));
         r3.add(P->Nx, P->row_tile, tw_x<T>(P, it.spec),
-               RowJob{Y, it.out, (int64_t)P->ncols * P->sy, P->sy, (int64_t)P->sx * P->sy, P->sx, P->sx, P->sy, 0, 0},
+               RowJob{Y, it.out, P->ncols * psy, 0, (int64_t)P->sx * P->sy, P->sx, P->sx, P->sy, 0, 0},
                it.nrhs);
     }
     bttb_status st;
@@ -482,7 +485,7 @@ bttb_status run_transpose(const std::vector<Item>& items, hipStream_t s, hipEven
         const bttb_plan_s* P = it.P;
         const WsLayout L = ws_layout(P, it.nrhs);
         r1.add(P->Nx, P->row_tile, tw_x<T>(P, it.spec),
-               RowJob{it.in, it.ws + L.tr_r, (int64_t)P->sx * P->sy, P->sx, (int64_t)P->ncols * P->sy, P->sy,
+               RowJob{it.in, it.ws + L.tr_r, (int64_t)P->sx * P->sy, P->sx, P->ncols * panel_rows(P->sy), 0,
                       P->sx, P->sy, 0, 0},
                it.nrhs);
         rounds = std::max(rounds, (P->nz + P->tr_chunk - 1) / P->tr_chunk);
@@ -502,19 +505,19 @@ bttb_status run_transpose(const std::vector<Item>& items, hipStream_t s, hipEven
             const WsLayout L = ws_layout(P, it.nrhs);
             const cT<T>* R = (const cT<T>*)(it.ws + L.tr_r);
             cT<T>* Z = (cT<T>*)(it.ws + L.tr_z);
+            const int64_t pny = panel_rows(P->ny), psy = panel_rows(P->sy);
             c2.add(ColKey{P->Ny, 0, P->col_tile, P->form}, tw_y<T>(P, it.spec),
-                   col_job(P, R, it.spec, Z, P->sy, P->ny, P->sy, P->ny, r0, nl, it.nrhs), nl);
+                   col_job(P, R, it.spec, Z, psy, pny, P->sy, P->ny, r0, nl, it.nrhs), nl);
             T* out = (T*)it.out;
             if (nl == P->nz) {
                 r3.add(P->Nx, P->row_tile, tw_x<T>(P, it.spec),
-                       RowJob{Z, out, (int64_t)P->ncols * P->ny, P->ny, (int64_t)P->nx * P->ny, P->nx, P->nx, P->ny,
-                              0, 0},
+                       RowJob{Z, out, P->ncols * pny, 0, (int64_t)P->nx * P->ny, P->nx, P->nx, P->ny, 0, 0},
                        it.nrhs * P->nz);
             } else {
                 for (int q = 0; q < it.nrhs; ++q)
                     r3.add(P->Nx, P->row_tile, tw_x<T>(P, it.spec),
-                           RowJob{Z + (size_t)q * nl * P->ncols * P->ny, out + ((size_t)q * P->nz + r0) * P->nx * P->ny,
-                                  (int64_t)P->ncols * P->ny, P->ny, (int64_t)P->nx * P->ny, P->nx, P->nx, P->ny, 0, 0},
+                           RowJob{Z + (size_t)q * nl * P->ncols * pny, out + ((size_t)q * P->nz + r0) * P->nx * P->ny,
+                                  P->ncols * pny, 0, (int64_t)P->nx * P->ny, P->nx, P->nx, P->ny, 0, 0},
                            nl);
             }
         }

@@ -27,6 +27,18 @@ struct GenParams {
     int sym, bx, by;
 };
 
+// Half spectra along x (packed: N/2 columns) of a block of R rows are stored
+// in panels of PANEL rows: element (kx, y) at
+// ((y / PANEL) * ncols + kx) * PANEL + y % PANEL, and the block takes
+// ncols * panel_rows(R) elements.  A row group of the row kernels then reads
+// or writes contiguous memory, and a column is PANEL-row segments.
+constexpr int PANEL = 8;
+__host__ __device__ constexpr int64_t panel_rows(int64_t r) { return (r + PANEL - 1) / PANEL * PANEL; }
+__host__ __device__ __forceinline__ int64_t pidx(int kx, int y, int ncols)
+{
+    return ((int64_t)(y / PANEL) * ncols + kx) * PANEL + (y % PANEL);
+}
+
 // Work tables.  A launch of a row or column kernel processes every job of
 // its table (one job per problem instance / right-hand-side batch, all with
 // the same transform length); the table is passed by value as a kernel
@@ -34,9 +46,10 @@ struct GenParams {
 constexpr int MAX_JOBS = 32;
 
 struct RowJob {
-    const void* in;       // real rows (r2c) or packed half spectra (c2r)
-    void* out;            // packed half spectra (r2c) or real rows (c2r)
-    int64_t in_bs, in_ld; // batch and row/column strides of the input (elements)
+    const void* in;       // real rows (r2c) or packed half spectra in panels (c2r)
+    void* out;            // packed half spectra in panels (r2c) or real rows (c2r)
+    int64_t in_bs, in_ld; // batch stride and row stride of the input (elements;
+                          // the row stride is unused for half spectra)
     int64_t out_bs, out_ld;
     int nv;               // r2c: valid input length of a row; c2r: output length
     int nrows;            // rows per batch
@@ -52,7 +65,8 @@ struct ColJob {
     const void* a;        // input columns: X (forward) or R (transpose)
     const void* spec;     // spectra of the job's plan
     void* b;              // output columns: Y (forward) or Z (transpose)
-    int64_t lda, ldb;     // column strides of a and b (elements)
+    int64_t lda, ldb;     // padded rows (panel_rows) of a and b: a block of one
+                          // layer / right-hand side is ncols * lda elements
     int na, nb;           // valid rows of a (ny or sy), rows written to b (sy or ny)
     int r0, nl;           // layers [r0, r0 + nl)
     int ncols, nrhs;

@@ -6,11 +6,11 @@
 //                    the closed-form prism integrals (Sec. 3, eq. Tcircpadded /
 //                    eq. Tcircpaddedgeneral; Sec. 4.1 / 4.2 entries)
 //   k_rows_r2c       real rows -> half spectra along x, pairs of rows packed
-//                    into one complex transform, written column-major
-//                    ([kx][row]) through an LDS tile
+//                    into one complex transform, written in 8-row panels
+//                    (bttb_internal.h) through an LDS tile
 //   k_cols_spec      FP64 column transforms of the generator -> stored spectra
 //                    (scaled by 1 / (Nx Ny), rounded to the working precision)
-//   k_rows_c2r       half spectra ([kx][row]) -> real rows along x, two rows per
+//   k_rows_c2r       half spectra (panels) -> real rows along x, two rows per
 //                    complex transform, extraction of the leading columns
 //
 // The column kernels of the products are in bttb_cols.hip.  All kernels take
@@ -180,8 +180,8 @@ template <typename T, int N, int P0 = 4> struct RowCfg {
 
 // Row transform, real -> packed half spectra, over every job of the table.
 // Job input: batch b, row y, column x at in[b * in_bs + y * in_ld + x],
-// x < nv valid (zero beyond, up to N); output: packed half spectra at
-// out[b * out_bs + kx * out_ld + y], kx < N/2, y < nrows.
+// x < nv valid (zero beyond, up to N); output: packed half spectra in
+// panels, out[b * out_bs + pidx(kx, y, N/2)], kx < N/2, y < nrows.
 template <typename TI, typename T, int N, int P0>
 __global__ void __launch_bounds__((RowCfg<T, N, P0>::THREADS))
 k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
@@ -251,7 +251,7 @@ k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
                     Cc = mk<T>((T)0.5 * (z.y + zr.y), (T)0.5 * (zr.x - z.x));
                 }
                 const int ra = row0 + 2 * q;
-                cT<T>* o = dst + (int64_t)kx * J.out_ld + ra;
+                cT<T>* o = dst + pidx(kx, ra, C::HALF);
                 if (ra + 1 < J.nrows && ((uintptr_t)o & 15) == 0) {
                     store_pair<T>(o, A, Cc);
                 } else {
@@ -293,7 +293,7 @@ k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
             for (int i = 0; i < 8; ++i) {
                 const int e = threadIdx.x + i * C::THREADS;   // HALF * RT = 8 * THREADS
                 const int kx = e / C::RT, rr = e % C::RT;
-                if (row0 + rr < J.nrows) dst[(int64_t)kx * J.out_ld + row0 + rr] = lds[kx * C::SROW + rr];
+                if (row0 + rr < J.nrows) dst[pidx(kx, row0 + rr, C::HALF)] = lds[kx * C::SROW + rr];
             }
         }
 #pragma unroll
@@ -302,7 +302,7 @@ k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
 }
 
 // Row transform, packed half spectra -> real rows, over every job of the
-// table.  Job input: in[b * in_bs + kx * in_ld + y], kx < N/2, y < nrows;
+// table.  Job input: in[b * in_bs + pidx(kx, y, N/2)], kx < N/2, y < nrows;
 // output: out[b * out_bs + y * out_ld + x] for x < nv (real, unnormalised
 // inverse transform; the 1/(Nx Ny) factor lives in the spectra).
 template <typename T, int N, int P0>
@@ -332,7 +332,7 @@ k_rows_c2r(RowJobs jobs, const cT<T>* __restrict__ tw)
         for (int i = 0; i < 8; ++i) {
             const int e = threadIdx.x + i * C::THREADS;
             const int kx = e / C::RT, rr = e % C::RT;
-            tl[i] = (row0 + rr < J.nrows) ? src[(int64_t)kx * J.in_ld + row0 + rr] : mk<T>(0, 0);
+            tl[i] = (row0 + rr < J.nrows) ? src[pidx(kx, row0 + rr, C::HALF)] : mk<T>(0, 0);
         }
     };
     int g = xcd_order(blockIdx.x, G);
@@ -469,7 +469,7 @@ k_rows_r2c_t(RowJobs jobs, const cT<T>* __restrict__ tw)
             cT<T>* dst = (cT<T>*)J.out + (int64_t)b * J.out_bs;
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                cT<T>* col = dst + (int64_t)(t + m * TPL) * J.out_ld + row0;
+                cT<T>* col = dst + pidx(t + m * TPL, row0, N / 2);   // row0 % PANEL == 0
 #pragma unroll
                 for (int rr = 0; rr < 8; ++rr)
                     if (row0 + rr < J.nrows) col[rr] = o[m][rr];
@@ -503,7 +503,7 @@ k_rows_c2r_t(RowJobs jobs, const cT<T>* __restrict__ tw)
         cT<T> c[4][8];   // c[m][row]: packed half spectrum at k = t + m TPL
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            const cT<T>* col = src + (int64_t)(t + m * TPL) * J.in_ld + row0;
+            const cT<T>* col = src + pidx(t + m * TPL, row0, N / 2);   // row0 % PANEL == 0
 #pragma unroll
             for (int rr = 0; rr < 8; ++rr) c[m][rr] = (live && row0 + rr < J.nrows) ? col[rr] : mk<T>(0, 0);
         }
@@ -558,8 +558,9 @@ k_rows_c2r_t(RowJobs jobs, const cT<T>* __restrict__ tw)
 // ---------------------------------------------------------------------------
 // column transforms
 // ---------------------------------------------------------------------------
-// spectra from the FP64 generator: in[(l * ncols + kx) * N + y] (l = layer in
-// batch, packed half spectra along x) -> FFT_y(in) * scale, stored as
+// spectra from the FP64 generator: in = packed half spectra along x of the
+// nl layers, N rows each, in panels (block l at in + l * ncols * N) ->
+// FFT_y(in) * scale, stored as
 //   FORM_COMPLEX:   spec[((r0 + l) * ncols + kx) * N + ky] (column 0 becomes
 //                   T^[0] + i T^[N/2], the packed pair of Hermitian columns)
 //   FORM_REAL_EVEN: the real parts for ky in [0, N/2] at
@@ -580,9 +581,9 @@ k_cols_spec(const double2* __restrict__ in, int ncols, void* __restrict__ spec, 
     const int l = blockIdx.y;
     const bool ok = col < ncols;
     double2 v[8];
-    const double2* src = in + ((int64_t)l * ncols + (ok ? col : 0)) * N;
+    const double2* src = in + (int64_t)l * ncols * N;
 #pragma unroll
-    for (int m = 0; m < 8; ++m) v[m] = ok ? src[t + m * TPL] : make_double2(0.0, 0.0);
+    for (int m = 0; m < 8; ++m) v[m] = ok ? src[pidx(col, t + m * TPL, ncols)] : make_double2(0.0, 0.0);
     LineTwiddles<double, N> twl;
     twl.load(tw, t);
     fft_line<double, N, -1, false>(v, lds + cl * lds_line_elems(N), twl, t);
