@@ -183,6 +183,9 @@ def main():
                     help="stored spectrum form (auto: real even for this gravity workload)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's default kernel configuration instead of the autotuner's")
+    ap.add_argument("--no-cgls", action="store_true", help="skip the CGLS (inversion driver) timing")
+    ap.add_argument("--cgls-iters", type=int, default=20)
+    ap.add_argument("--cgls-lambda", type=float, default=1.0)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes 3 times (calibrates the "
                          "HBM byte counters of a profiler against a kernel of known traffic)")
@@ -273,6 +276,31 @@ def main():
     # sampled stations / prisms for the oracle (CPU baseline and parity sample)
     d32 = g32["d"].double().cpu().numpy()
     mt32 = g32["mt"].double().cpu().numpy()
+    if not args.no_cgls:
+        # the inversion driver on the same plan: CGLS steps (one G p, one
+        # G^T r and the vector kernels each) fitting the forward data
+        log("cgls run")
+        plan = g32["plan"]
+        lam = args.cgls_lambda
+        plan.cgls(g32["d"], lam, 1)                     # warm-up
+        torch.cuda.synchronize()
+
+        def timed(k):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            _, hist = plan.cgls(g32["d"], lam, k)
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1), hist.cpu().numpy()
+        k1, k2 = max(1, args.cgls_iters // 2), args.cgls_iters
+        t1, _ = timed(k1)
+        t2, h = timed(k2)
+        J = h[:, 0] + lam * lam * h[:, 1]
+        # per step: the difference of two runs (cancels the start and the
+        # per-call allocations)
+        result["cgls"] = {"iterations": k2, "lambda": lam,
+                          "ms_per_iteration": round((t2 - t1) / (k2 - k1), 4) if k2 > k1 else None,
+                          "objective_start": float(J[0]), "objective_end": float(J[-1])}
     if not args.no_fp64:
         log("fp64 run")
         del g32

@@ -177,6 +177,38 @@ bttb_status bttb_transpose(bttb_plan_t plan, const void* spectra, const void* r,
                            int32_t nrhs, void* workspace, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Inversion driver: the regularised least-squares problem
+ *     min_m ||G m - d||^2 + lambda^2 ||m||^2
+ * that the transpose product exists for (Sec. 1: conjugate gradients with
+ * FFT-based products; Sec. 7: use in the inverse problem), solved by CGLS,
+ * conjugate gradients on the normal equations (G^T G + lambda^2 I) m = G^T d
+ * without forming G^T G:
+ *   r = d - G m,  s = G^T r - lambda^2 m,  p = s,  gamma = ||s||^2;  per step
+ *   q = G p,  alpha = gamma / (||q||^2 + lambda^2 ||p||^2),
+ *   m += alpha p,  r -= alpha q,  s = G^T r - lambda^2 m,
+ *   beta = ||s||^2 / gamma,  p = s + beta p.
+ * Every step runs on the device (the product kernels plus FP64-accumulating
+ * vector kernels); scalars stay on the device, so the call does not
+ * synchronise and can be captured in a graph.
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes of bttb_cgls for this plan (one right-hand side).
+ * Errors: NULL_POINTER. */
+bttb_status bttb_cgls_query(bttb_plan_t plan, size_t* workspace_bytes);
+
+/* Run `iterations` CGLS steps from the initial model in m.
+ * d: device [sy][sx] (plan precision, not modified); m: device [nz][ny][nx],
+ * the initial guess on entry and the result on exit; lambda >= 0;
+ * history: optional device array of 3 (iterations + 1) doubles receiving,
+ * after the start and after each step k, (||r_k||^2, ||m_k||^2, ||s_k||^2)
+ * (||r||^2 + lambda^2 ||m||^2 does not increase); workspace: device,
+ * >= bttb_cgls_query bytes, 16-byte aligned; spectra from
+ * bttb_kernel_generate.  Errors: NULL_POINTER, INVALID_VALUE,
+ * WORKSPACE_TOO_SMALL, HIP. */
+bttb_status bttb_cgls(bttb_plan_t plan, const void* spectra, const void* d, void* m, double lambda,
+                      int32_t iterations, double* history, void* workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batches: many problems (uneven sizes, gravity and magnetic mixed, one
  * precision) run together.  Every stage of the products is launched once per
  * transform length with a work table covering all problems of that length,

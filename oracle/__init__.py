@@ -15,7 +15,9 @@ eq. continuousforwardmodel / eq. Gslice of Hogue, Renaut & Vatankhah):
                       dense matrix (Sec. 5: the direct products the paper
                       compares against);
 * ``station_sums`` / ``prism_sums`` -- single rows / columns of G m and G^T r
-                      for volumes too large for a dense G.
+                      for volumes too large for a dense G;
+* ``regularized_lsq`` -- the minimiser of ||G m - d||^2 + lam^2 ||m||^2 from
+                      the dense normal equations (checks the inversion driver).
 
 The magnetic kernel is the total-field anomaly of induced magnetisation
 (Sec. 4.2); the gravity kernel is g_z (Sec. 4.1).  Conventions (0-based):
@@ -272,3 +274,12 @@ def prism_sums(P: Problem, v: np.ndarray, prisms) -> np.ndarray:
     ps = P.c_struct()
     _lib().orc_prism_sums(ctypes.byref(ps), _dptr(vv), pqr.shape[0], _iptr(pqr), _dptr(out))
     return out
+
+
+def regularized_lsq(G: np.ndarray, d: np.ndarray, lam: float) -> np.ndarray:
+    """The minimiser of ||G m - d||^2 + lam^2 ||m||^2 (the regularised inverse
+    problem the transpose product serves, Sec. 1 and Sec. 7): the solution of
+    the normal equations (G^T G + lam^2 I) m = G^T d by a dense FP64 solve."""
+    G = np.asarray(G, dtype=np.float64)
+    A = G.T @ G + lam * lam * np.eye(G.shape[1])
+    return np.linalg.solve(A, G.T @ np.asarray(d, dtype=np.float64).ravel())

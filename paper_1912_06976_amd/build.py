@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.environ.get("BTTB_LIB_OUT", os.path.join(HERE, "libbttb.so"))
 BUILD = os.environ.get("BTTB_BUILD_DIR", os.path.join(ROOT, "_build"))
-SOURCES = ["bttb_kernels.hip", "bttb_cols.hip", "bttb_host.hip"]
+SOURCES = ["bttb_kernels.hip", "bttb_cols.hip", "bttb_cgls.hip", "bttb_host.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("BTTB_ARCH", "gfx950")

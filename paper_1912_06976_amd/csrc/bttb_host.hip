@@ -539,6 +539,75 @@ bttb_status run_single(bool fwd, const bttb_plan_s* P, const char* spec, const v
     return fwd ? run_forward<T>(items, s, ev) : run_transpose<T>(items, s, ev);
 }
 
+// CGLS workspace: the products' workspace, the vectors r, q (data size),
+// s, p (model size), five arrays of reduction partials and the scalars
+struct CglsLayout {
+    size_t prod, r, q, s, p, part, scal, total;
+    int nb;
+    int64_t n, nd;
+};
+
+CglsLayout cgls_layout(const bttb_plan_s* P)
+{
+    CglsLayout L{};
+    L.n = (int64_t)P->nx * P->ny * P->nz;
+    L.nd = (int64_t)P->sx * P->sy;
+    const int64_t big = std::max(L.n, L.nd);
+    L.nb = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (big + 256 * 8 - 1) / (256 * 8)));
+    L.prod = 0;
+    L.r = align_up(ws_layout(P, 1).total);
+    L.q = align_up(L.r + (size_t)L.nd * P->esz);
+    L.s = align_up(L.q + (size_t)L.nd * P->esz);
+    L.p = align_up(L.s + (size_t)L.n * P->esz);
+    L.part = align_up(L.p + (size_t)L.n * P->esz);
+    L.scal = align_up(L.part + 5 * (size_t)L.nb * sizeof(double));
+    L.total = align_up(L.scal + sizeof(CglsScalars));
+    return L;
+}
+
+// init: r = d - G m, s = G^T r - lambda^2 m, p = s; then `iters` steps
+//   q = G p; alpha = gamma / (||q||^2 + lambda^2 ||p||^2);
+//   m += alpha p; r -= alpha q; s = G^T r - lambda^2 m;
+//   beta = ||s||^2 / gamma; p = s + beta p
+template <typename T>
+bttb_status run_cgls(const bttb_plan_s* P, const char* spec, const T* d, T* m, double lam, int iters, double* hist,
+                     char* ws, hipStream_t st)
+{
+    const CglsLayout L = cgls_layout(P);
+    char* wp = ws + L.prod;
+    T* r = (T*)(ws + L.r);
+    T* q = (T*)(ws + L.q);
+    T* sv = (T*)(ws + L.s);
+    T* p = (T*)(ws + L.p);
+    double* part = (double*)(ws + L.part);
+    double *pq = part, *pp = part + L.nb, *ps = part + 2 * L.nb, *pr = part + 3 * L.nb, *pm = part + 4 * L.nb;
+    CglsScalars* sc = (CglsScalars*)(ws + L.scal);
+    const double lam2 = lam * lam;
+    const int nb = L.nb;
+    bttb_status e;
+#define CG(x, what) if ((e = (x)) != BTTB_OK) return e
+#define CGH(x, what) if ((e = hip_check((x), what)) != BTTB_OK) return e
+    CG(run_single<T>(true, P, spec, m, q, 1, wp, st), "forward");
+    CGH(launch_cgls_residual<T>(d, q, r, L.nd, pr, nb, st), "cgls residual");
+    CG(run_single<T>(false, P, spec, r, sv, 1, wp, st), "transpose");
+    CGH(launch_cgls_grad<T>(sv, m, lam2, L.n, ps, pm, nb, st), "cgls gradient");
+    CGH(launch_cgls_beta(ps, pr, pm, nb, sc, hist, 0, 1, st), "cgls scalars");
+    CGH(launch_cgls_direction<T>(sv, p, L.n, sc, 1, pp, nb, st), "cgls direction");
+    for (int k = 1; k <= iters; ++k) {
+        CG(run_single<T>(true, P, spec, p, q, 1, wp, st), "forward");
+        CGH(launch_cgls_dot<T>(q, q, L.nd, pq, nb, st), "cgls dot");
+        CGH(launch_cgls_alpha(pq, pp, nb, lam2, sc, st), "cgls scalars");
+        CGH(launch_cgls_step<T>(m, p, L.n, r, q, L.nd, sc, pr, nb, st), "cgls step");
+        CG(run_single<T>(false, P, spec, r, sv, 1, wp, st), "transpose");
+        CGH(launch_cgls_grad<T>(sv, m, lam2, L.n, ps, pm, nb, st), "cgls gradient");
+        CGH(launch_cgls_beta(ps, pr, pm, nb, sc, hist, k, 0, st), "cgls scalars");
+        CGH(launch_cgls_direction<T>(sv, p, L.n, sc, 0, pp, nb, st), "cgls direction");
+    }
+#undef CG
+#undef CGH
+    return BTTB_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -687,6 +756,38 @@ bttb_status bttb_transpose_profiled(bttb_plan_t plan, const void* spectra, const
         return profiled(false, plan, spectra, r, mt, nrhs, workspace, ws_bytes, stream, kernel_ms);
     } catch (...) {
         return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_transpose_profiled");
+    }
+}
+
+bttb_status bttb_cgls_query(bttb_plan_t plan, size_t* workspace_bytes)
+{
+    g_last_error.clear();
+    if (!plan || !workspace_bytes) return fail(BTTB_ERR_NULL_POINTER, "plan and workspace_bytes must not be NULL");
+    *workspace_bytes = cgls_layout(plan).total;
+    return BTTB_OK;
+}
+
+bttb_status bttb_cgls(bttb_plan_t plan, const void* spectra, const void* d, void* m, double lambda,
+                      int32_t iterations, double* history, void* workspace, size_t ws_bytes, void* stream)
+{
+    try {
+        g_last_error.clear();
+        if (!plan || !spectra || !d || !m || !workspace)
+            return fail(BTTB_ERR_NULL_POINTER, "plan, spectra, d, m and workspace must not be NULL");
+        if (!std::isfinite(lambda) || lambda < 0.0) return fail(BTTB_ERR_INVALID_VALUE, "lambda must be finite and >= 0");
+        if (iterations < 0) return fail(BTTB_ERR_INVALID_VALUE, "iterations must be >= 0");
+        if (ws_bytes < cgls_layout(plan).total)
+            return fail(BTTB_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than bttb_cgls_query reports");
+        if (!aligned(spectra, kAlign) || !aligned(workspace, 16) || !aligned(d, plan->esz) || !aligned(m, plan->esz))
+            return fail(BTTB_ERR_INVALID_VALUE,
+                        "spectra must be 256-byte aligned, workspace 16-byte aligned, d and m element aligned");
+        hipStream_t s = (hipStream_t)stream;
+        return plan->fp64 ? run_cgls<double>(plan, (const char*)spectra, (const double*)d, (double*)m, lambda,
+                                             iterations, history, (char*)workspace, s)
+                          : run_cgls<float>(plan, (const char*)spectra, (const float*)d, (float*)m, lambda,
+                                            iterations, history, (char*)workspace, s);
+    } catch (...) {
+        return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_cgls");
     }
 }
 

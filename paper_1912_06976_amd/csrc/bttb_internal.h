@@ -80,6 +80,9 @@ struct ColJobs {
     int njobs, total;     // total = blocks of all jobs
 };
 
+// device scalars of the CGLS iteration
+struct CglsScalars { double gamma, alpha, beta, pad; };
+
 template <typename T> struct cplx;
 template <> struct cplx<float> { using type = float2; };
 template <> struct cplx<double> { using type = double2; };
@@ -105,5 +108,22 @@ template <typename T, int ACC>
 hipError_t launch_cols_fwd(int N, int tile, int form, const ColJobs& jobs, const cT<T>* tw, hipStream_t s);
 template <typename T>
 hipError_t launch_cols_tr(int N, int tile, int form, const ColJobs& jobs, const cT<T>* tw, hipStream_t s);
+
+// CGLS vector kernels (nb blocks; each reduction writes nb FP64 partials)
+template <typename T> hipError_t launch_cgls_dot(const T* a, const T* b, int64_t n, double* out, int nb, hipStream_t s);
+template <typename T>
+hipError_t launch_cgls_residual(const T* d, const T* q, T* r, int64_t n, double* out, int nb, hipStream_t s);
+template <typename T>
+hipError_t launch_cgls_grad(T* sv, const T* m, double lam2, int64_t n, double* out_s, double* out_m, int nb,
+                            hipStream_t s);
+template <typename T>
+hipError_t launch_cgls_direction(const T* sv, T* p, int64_t n, const CglsScalars* sc, int first, double* out, int nb,
+                                 hipStream_t s);
+template <typename T>
+hipError_t launch_cgls_step(T* m, const T* p, int64_t n, T* r, const T* q, int64_t nd, const CglsScalars* sc,
+                            double* out, int nb, hipStream_t s);
+hipError_t launch_cgls_alpha(const double* pq, const double* pp, int nb, double lam2, CglsScalars* sc, hipStream_t s);
+hipError_t launch_cgls_beta(const double* ps, const double* pr, const double* pm, int nb, CglsScalars* sc,
+                            double* hist, int k, int first, hipStream_t s);
 
 }  // namespace bttbk

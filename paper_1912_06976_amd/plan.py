@@ -128,6 +128,24 @@ def bttb_transpose_profiled(plan: int, spectra, r, mt, nrhs: int, workspace, str
     return _profiled("bttb_transpose_profiled", plan, spectra, r, mt, nrhs, workspace, stream)
 
 
+def bttb_cgls_query(plan: int) -> int:
+    """Workspace bytes of bttb_cgls for this plan."""
+    sz = ctypes.c_size_t()
+    check("bttb_cgls_query", _lib.load().bttb_cgls_query(ctypes.c_void_p(plan), ctypes.byref(sz)))
+    return sz.value
+
+
+def bttb_cgls(plan: int, spectra: torch.Tensor, d: torch.Tensor, m: torch.Tensor, lam: float, iterations: int,
+              history: torch.Tensor | None, workspace: torch.Tensor, stream=None) -> None:
+    """CGLS for min ||G m - d||^2 + lam^2 ||m||^2, m updated in place; history
+    (optional, float64 [iterations + 1, 3]) receives (||r||^2, ||m||^2, ||s||^2)."""
+    hp = _ptr(history) if history is not None else ctypes.c_void_p(0)
+    check("bttb_cgls",
+          _lib.load().bttb_cgls(ctypes.c_void_p(plan), _ptr(spectra), _ptr(d), _ptr(m), float(lam), int(iterations),
+                                hp, _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                _stream_ptr(stream)))
+
+
 def bttb_debug_generator(plan: int, layer: int, workspace: torch.Tensor, stream=None) -> np.ndarray:
     _, _, nx, ny = bttb_plan_query(plan, 1)
     out = np.empty((ny, nx), dtype=np.float64)
@@ -215,6 +233,26 @@ class Plan:
         self._check_vec(out, (self.nz, self.ny, self.nx), "out")
         bttb_transpose(self.handle, self.spectra, r, out, nrhs, self.workspace(nrhs), stream)
         return out
+
+    def cgls(self, d: torch.Tensor, lam: float, iterations: int, m0: torch.Tensor | None = None, stream=None):
+        """Regularised least squares min ||G m - d||^2 + lam^2 ||m||^2 by CGLS on
+        the device (one forward and one transpose product per step).  Returns
+        (m, history) with history a float64 tensor [iterations + 1, 3] of
+        (||r||^2, ||m||^2, ||s||^2)."""
+        if self.spectra is None:
+            raise RuntimeError("call generate() first")
+        self._check_vec(d, (self.sy, self.sx), "d")
+        if d.dim() != 2:
+            raise ValueError("d must be [sy, sx] (one right-hand side)")
+        if m0 is None:
+            m = torch.zeros((self.nz, self.ny, self.nx), dtype=self.dtype, device=d.device)
+        else:
+            self._check_vec(m0, (self.nz, self.ny, self.nx), "m0")
+            m = m0.clone()
+        hist = torch.zeros((iterations + 1, 3), dtype=torch.float64, device=d.device)
+        ws = torch.empty(bttb_cgls_query(self.handle), dtype=torch.uint8, device=d.device)
+        bttb_cgls(self.handle, self.spectra, d, m, lam, iterations, hist, ws, stream)
+        return m, hist
 
     def debug_generator(self, layer: int) -> np.ndarray:
         return bttb_debug_generator(self.handle, layer, self.workspace(1))

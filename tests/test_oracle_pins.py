@@ -449,3 +449,28 @@ def test_dense_product_equals_library_fft_convolution(oracle_lib):
     lhs = float(ref @ v.ravel())
     rhs = float(m.ravel() @ reft)
     assert abs(lhs - rhs) <= 1e-13 * np.linalg.norm(ref) * np.linalg.norm(v)
+
+
+def test_regularized_lsq_matches_svd_filter_factors_and_augmented_lstsq(oracle_lib):
+    # the minimiser of ||G m - d||^2 + lam^2 ||m||^2 has the closed form
+    # sum_i s_i / (s_i^2 + lam^2) (u_i^T d) v_i (Tikhonov filter factors) and
+    # is the least-squares solution of the stacked system [G; lam I] m = [d; 0]
+    import oracle
+    import scipy.linalg
+    P = oracle.problem_from_dict(W.small_gravity())
+    G = oracle.dense_G(P)
+    rng = np.random.default_rng(5)
+    d = G @ rng.uniform(0, 1, G.shape[1]) + 0.01 * rng.standard_normal(G.shape[0])
+    U, sv, Vt = np.linalg.svd(G, full_matrices=False)
+    for lam in (0.3 * sv[0], 0.05 * sv[0], 1e-3 * sv[0]):
+        m = oracle.regularized_lsq(G, d, lam)
+        m_svd = Vt.T @ (sv / (sv ** 2 + lam ** 2) * (U.T @ d))
+        A = np.vstack([G, lam * np.eye(G.shape[1])])
+        m_ls = scipy.linalg.lstsq(A, np.concatenate([d, np.zeros(G.shape[1])]))[0]
+        for other in (m_svd, m_ls):
+            assert np.linalg.norm(m - other) <= 1e-9 * np.linalg.norm(other)
+    # a large lam gives m -> G^T d / lam^2
+    lam = 1e4 * sv[0]
+    m = oracle.regularized_lsq(G, d, lam)
+    ref = G.T @ d / lam ** 2
+    assert np.linalg.norm(m - ref) <= 1e-6 * np.linalg.norm(ref)
