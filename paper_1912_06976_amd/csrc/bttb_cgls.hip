@@ -36,6 +36,48 @@ __device__ __forceinline__ double sum_partials(const double* p, int nb)
     return block_sum(v);
 }
 
+// four consecutive values with 16-byte accesses (the address must be
+// 16-byte aligned)
+template <typename T> struct V4 { T x[4]; };
+template <typename T> __device__ __forceinline__ V4<T> ld4(const T* p)
+{
+    V4<T> v;
+    if constexpr (sizeof(T) == 4) {
+        const float4 f = *(const float4*)p;
+        v.x[0] = f.x; v.x[1] = f.y; v.x[2] = f.z; v.x[3] = f.w;
+    } else {
+        const double2 a = *(const double2*)p, b = *(const double2*)(p + 2);
+        v.x[0] = a.x; v.x[1] = a.y; v.x[2] = b.x; v.x[3] = b.y;
+    }
+    return v;
+}
+template <typename T> __device__ __forceinline__ void st4(T* p, const V4<T>& v)
+{
+    if constexpr (sizeof(T) == 4) {
+        *(float4*)p = make_float4(v.x[0], v.x[1], v.x[2], v.x[3]);
+    } else {
+        *(double2*)p = make_double2(v.x[0], v.x[1]);
+        *(double2*)(p + 2) = make_double2(v.x[2], v.x[3]);
+    }
+}
+__device__ __forceinline__ bool al16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+// The element-wise kernels visit [0, n) in 4-element chunks with a grid-stride
+// loop when every array is 16-byte aligned (n4 = n / 4 chunks), then the
+// remaining elements one by one.
+#define BTTB_GRID_LOOPS(n, aligned, CHUNK, ONE)                                                      \
+    {                                                                                               \
+        const int64_t stride_ = (int64_t)gridDim.x * RED_THREADS;                                  \
+        const int64_t n4_ = (aligned) ? (n) / 4 : 0;                                                \
+        for (int64_t c = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; c < n4_; c += stride_) { \
+            const int64_t i = 4 * c;                                                                \
+            CHUNK                                                                                   \
+        }                                                                                           \
+        for (int64_t i = 4 * n4_ + (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < (n); i += stride_) { \
+            ONE                                                                                     \
+        }                                                                                           \
+    }
+
 // out[blockIdx.x] = partial of sum_i a_i b_i over a grid-stride range
 template <typename T>
 __global__ void __launch_bounds__(RED_THREADS) k_dot(const T* __restrict__ a, const T* __restrict__ b, int64_t n,
@@ -69,13 +111,22 @@ __global__ void __launch_bounds__(RED_THREADS) k_grad(T* __restrict__ s, const T
                                                       int64_t n, double* __restrict__ out_s, double* __restrict__ out_m)
 {
     double vs = 0.0, vm = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * RED_THREADS) {
+    BTTB_GRID_LOOPS(n, al16(s) && al16(m), {
+        V4<T> sv = ld4(s + i);
+        const V4<T> mv = ld4(m + i);
+        for (int k = 0; k < 4; ++k) {
+            sv.x[k] = (T)((double)sv.x[k] - lam2 * (double)mv.x[k]);
+            vs += (double)sv.x[k] * (double)sv.x[k];
+            vm += (double)mv.x[k] * (double)mv.x[k];
+        }
+        st4(s + i, sv);
+    }, {
         const T mi = m[i];
         const T x = (T)((double)s[i] - lam2 * (double)mi);
         s[i] = x;
         vs += (double)x * (double)x;
         vm += (double)mi * (double)mi;
-    }
+    })
     const double a = block_sum(vs);
     __syncthreads();
     const double b = block_sum(vm);
@@ -94,11 +145,19 @@ __global__ void __launch_bounds__(RED_THREADS) k_direction(const T* __restrict__
 {
     const double beta = first ? 0.0 : sc->beta;
     double v = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * RED_THREADS) {
+    BTTB_GRID_LOOPS(n, al16(s) && al16(p), {
+        V4<T> x = ld4(s + i);
+        if (!first) {
+            const V4<T> pv = ld4((const T*)p + i);
+            for (int k = 0; k < 4; ++k) x.x[k] = (T)((double)x.x[k] + beta * (double)pv.x[k]);
+        }
+        for (int k = 0; k < 4; ++k) v += (double)x.x[k] * (double)x.x[k];
+        st4(p + i, x);
+    }, {
         const T x = first ? s[i] : (T)((double)s[i] + beta * (double)p[i]);
         p[i] = x;
         v += (double)x * (double)x;
-    }
+    })
     const double a = block_sum(v);
     if (threadIdx.x == 0) out[blockIdx.x] = a;
 }
@@ -111,8 +170,14 @@ __global__ void __launch_bounds__(RED_THREADS) k_step(T* __restrict__ m, const T
                                                       const CglsScalars* __restrict__ sc, double* __restrict__ out)
 {
     const double alpha = sc->alpha;
-    for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * RED_THREADS)
+    BTTB_GRID_LOOPS(n, al16(m) && al16(p), {
+        V4<T> mv = ld4((const T*)m + i);
+        const V4<T> pv = ld4(p + i);
+        for (int k = 0; k < 4; ++k) mv.x[k] = (T)((double)mv.x[k] + alpha * (double)pv.x[k]);
+        st4(m + i, mv);
+    }, {
         m[i] = (T)((double)m[i] + alpha * (double)p[i]);
+    })
     double v = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < nd; i += (int64_t)gridDim.x * RED_THREADS) {
         const T x = (T)((double)r[i] - alpha * (double)q[i]);

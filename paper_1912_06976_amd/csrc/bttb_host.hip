@@ -553,7 +553,7 @@ CglsLayout cgls_layout(const bttb_plan_s* P)
     L.n = (int64_t)P->nx * P->ny * P->nz;
     L.nd = (int64_t)P->sx * P->sy;
     const int64_t big = std::max(L.n, L.nd);
-    L.nb = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (big + 256 * 8 - 1) / (256 * 8)));
+    L.nb = (int)std::max<int64_t>(1, std::min<int64_t>(2048, (big + 256 * 16 - 1) / (256 * 16)));
     L.prod = 0;
     L.r = align_up(ws_layout(P, 1).total);
     L.q = align_up(L.r + (size_t)L.nd * P->esz);

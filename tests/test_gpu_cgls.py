@@ -76,13 +76,13 @@ def test_cgls_warm_start_zero_steps_and_validation(torch_cuda):
     assert abs(hist[0, 0].item() - r0 @ r0) <= 1e-10 * (r0 @ r0)
     # a warm start continues the same minimisation
     lam = 0.2 * sv[0]
-    m1, _ = plan.cgls(dt, lam, 40)
-    m2, _ = plan.cgls(dt, lam, 40, m0=m1)
+    m1, _ = plan.cgls(dt, lam, 8)
+    m2, _ = plan.cgls(dt, lam, 8, m0=m1)
     import oracle
     ref = oracle.regularized_lsq(G, d, lam)
     e1 = np.linalg.norm(m1.cpu().numpy().ravel() - ref)
     e2 = np.linalg.norm(m2.cpu().numpy().ravel() - ref)
-    assert e2 <= e1
+    assert e2 <= 0.5 * e1
     ws = torch.empty(B.bttb_cgls_query(plan.handle), dtype=torch.uint8, device="cuda")
     with pytest.raises(B.BttbError):
         B.bttb_cgls(plan.handle, plan.spectra, dt, m1, -1.0, 5, None, ws)
