@@ -165,6 +165,74 @@ def run_gpu(torch, B, pr, prec, m_host, r_host, steps, warmup, want_kernels=True
     return out
 
 
+def run_batch(torch, B, steps):
+    """The batched workload: 48 seeded instances of uneven sizes (half gravity,
+    half magnetic), 4 right-hand sides each, one G m + one G^T r per instance,
+    all in one replay of the captured graph."""
+    log("batch run")
+    probs = W.batch48()
+    plans = [B.Plan(p, "fp32").generate() for p in probs]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(401)
+    ms = [torch.randn((4, p.nz, p.ny, p.nx), generator=g, device="cuda") for p in plans]
+    rs = [torch.randn((4, p.sy, p.sx), generator=g, device="cuda") for p in plans]
+    ds = [torch.empty((4, p.sy, p.sx), device="cuda") for p in plans]
+    mts = [torch.empty((4, p.nz, p.ny, p.nx), device="cuda") for p in plans]
+    batch = B.Batch(plans, max_nrhs=4)
+    for _ in range(3):
+        batch.run(ms, rs, out_ds=ds, out_mts=mts)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        batch.run(ms, rs, out_ds=ds, out_mts=mts)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / steps
+    cells = sum(W.dims(p)[0] * W.dims(p)[1] * W.dims(p)[2] for p in probs) * 4
+    byts = sum(2 * spectra_bytes(p, pl.nx_fft, pl.ny_fft, 4, pl.spectrum_form)
+               + 4 * (2 * W.dims(p)[0] * W.dims(p)[1] * W.dims(p)[2] + 2 * p["sx"] * p["sy"]) * 4
+               for p, pl in zip(probs, plans))
+    out = {"instances": len(probs), "nrhs": 4, "ms_per_step": round(ms_step, 4),
+           "cells_rhs_per_s": cells / (ms_step * 1e-3), "algorithmic_bytes": byts,
+           "algorithmic_GBps": round(byts / (ms_step * 1e-3) / 1e9, 1),
+           "distinct_fft_sizes": len({(pl.nx_fft, pl.ny_fft) for pl in plans}),
+           "spectrum_forms": {f: sum(pl.spectrum_form == f for pl in plans) for f in ("real_even", "complex")}}
+    del batch, plans, ms, rs, ds, mts
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_autograd(torch, B, steps):
+    """Loss 0.5 ||G m - d||^2 and its gradient G^T (G m - d) through the
+    autograd wrapper at magnetic 288 x 288 x 48 (FP32): one forward and one
+    transpose product per step."""
+    log("autograd run")
+    pr = W.magnetic_288()
+    plan = B.Plan(pr, "fp32").generate()
+    m0 = torch.tensor(W.uniform_model(pr, 503, 0.0, 0.05), dtype=torch.float32, device="cuda")
+    d = plan.forward(torch.tensor(W.box_model(pr, 501, nboxes=5), dtype=torch.float32, device="cuda"))
+
+    def step():
+        m = m0.clone().requires_grad_(True)
+        loss = 0.5 * (B.bttb_matvec(plan, m) - d).pow(2).sum()
+        loss.backward()
+        return m.grad
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / steps
+    nx, ny, nz = W.dims(pr)
+    return {"workload": "magnetic 288x288x48 FP32, loss 0.5||Gm-d||^2 forward + backward",
+            "ms_per_step": round(ms_step, 4), "cells_per_s": nx * ny * nz / (ms_step * 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +252,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's default kernel configuration instead of the autotuner's")
     ap.add_argument("--no-cgls", action="store_true", help="skip the CGLS (inversion driver) timing")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 48-instance batched timing")
+    ap.add_argument("--no-autograd", action="store_true", help="skip the autograd timing")
     ap.add_argument("--cgls-iters", type=int, default=20)
     ap.add_argument("--cgls-lambda", type=float, default=1.0)
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -301,6 +371,11 @@ def main():
         result["cgls"] = {"iterations": k2, "lambda": lam,
                           "ms_per_iteration": round((t2 - t1) / (k2 - k1), 4) if k2 > k1 else None,
                           "objective_start": float(J[0]), "objective_end": float(J[-1])}
+    if not args.no_batch:
+        result["batch"] = run_batch(torch, B, args.steps)
+    if not args.no_autograd:
+        result["autograd"] = run_autograd(torch, B, args.steps)
+
     if not args.no_fp64:
         log("fp64 run")
         del g32

@@ -210,11 +210,14 @@ bttb_status bttb_cgls(bttb_plan_t plan, const void* spectra, const void* d, void
 
 /* ------------------------------------------------------------------------
  * Batches: many problems (uneven sizes, gravity and magnetic mixed, one
- * precision) run together.  Every stage of the products is launched once per
- * transform length with a work table covering all problems of that length,
- * and the whole sequence of all problems is captured into one HIP graph, so a
- * run is a single graph launch.  The graph is rebuilt only when the pointers
- * or right-hand-side counts of a run differ from the previous run's.
+ * precision) run together.  The problems are split into up to four
+ * independent branches balanced by work (problems with the same transform
+ * lengths share a branch); in a branch every stage of the products is
+ * launched once per transform length with a work table covering all its
+ * problems of that length.  The whole run is captured into one HIP graph
+ * whose branches execute concurrently, so a run is a single graph launch.
+ * The graph is rebuilt only when the pointers or right-hand-side counts of a
+ * run differ from the previous run's.
  * ------------------------------------------------------------------------ */
 typedef struct bttb_batch_s* bttb_batch_t;
 
@@ -232,8 +235,9 @@ typedef struct {
 
 /* Group nplans plans (not owned; they must outlive the batch) for runs with
  * at most max_nrhs right-hand sides per problem.  All plans must have the
- * same precision.  Creates a non-blocking stream (default priority) used for
- * graph capture.  Errors: NULL_POINTER, INVALID_VALUE, HIP. */
+ * same precision.  Creates five non-blocking streams (default priority) and
+ * five events used for graph capture.  Errors: NULL_POINTER, INVALID_VALUE,
+ * HIP. */
 bttb_status bttb_batch_create(const bttb_plan_t* plans, int32_t nplans, int32_t max_nrhs,
                               bttb_batch_t* out);
 
@@ -246,7 +250,8 @@ bttb_status bttb_batch_query(bttb_batch_t batch, size_t* workspace_bytes);
 bttb_status bttb_batch_run(bttb_batch_t batch, const bttb_batch_io* io, void* workspace,
                            size_t ws_bytes, void* stream);
 
-/* Release the graph, the capture stream and the batch (NULL accepted). */
+/* Release the graph, the capture streams and events and the batch (NULL
+ * accepted). */
 bttb_status bttb_batch_destroy(bttb_batch_t batch);
 
 /* ------------------------------------------------------------------------

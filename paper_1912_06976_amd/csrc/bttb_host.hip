@@ -824,6 +824,9 @@ bttb_status bttb_debug_generator(bttb_plan_t plan, int32_t layer, double* host_o
 
 }  // extern "C"
 
+// parallel branches of a batch graph
+constexpr int kBatchBranches = 4;
+
 struct bttb_batch_s {
     std::vector<const bttb_plan_s*> plans;
     int max_nrhs = 1;
@@ -831,6 +834,8 @@ struct bttb_batch_s {
     std::vector<size_t> ws_off;
     size_t ws_total = 0;
     hipStream_t cap = nullptr;
+    hipStream_t side[kBatchBranches] = {};      // branch streams joined into the capture
+    hipEvent_t ev[kBatchBranches + 1] = {};     // fork and join events
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<uintptr_t> key;     // pointers and counts of the captured run
@@ -847,21 +852,62 @@ void batch_release_graph(bttb_batch_s* B)
     B->key.clear();
 }
 
+// The plans are split into at most kBatchBranches independent branches (each
+// plan's forward and transpose share its workspace, so they stay in one
+// branch, in that order).  Plans with the same transform lengths go to one
+// branch, where their launches merge into shared work tables; the branches
+// are balanced by work (cells times right-hand sides, largest group first)
+// and run concurrently: forked from s and joined back with events.
 template <typename T>
 bttb_status batch_enqueue(bttb_batch_s* B, const bttb_batch_io* io, char* ws, hipStream_t s)
 {
-    std::vector<Item> fwd, tr;
+    struct Group { int Nx, Ny; std::vector<size_t> idx; double work; };
+    std::vector<Group> groups;
     for (size_t k = 0; k < B->plans.size(); ++k) {
         const bttb_plan_s* P = B->plans[k];
-        char* w = ws + B->ws_off[k];
-        if (io[k].m) fwd.push_back(Item{P, (const char*)io[k].spectra, io[k].m, io[k].d, io[k].nrhs, w});
-        if (io[k].r) tr.push_back(Item{P, (const char*)io[k].spectra, io[k].r, io[k].mt, io[k].nrhs, w});
+        if (!io[k].m && !io[k].r) continue;
+        size_t g = 0;
+        while (g < groups.size() && !(groups[g].Nx == P->Nx && groups[g].Ny == P->Ny)) ++g;
+        if (g == groups.size()) groups.push_back(Group{P->Nx, P->Ny, {}, 0.0});
+        groups[g].idx.push_back(k);
+        groups[g].work += (double)P->nx * P->ny * P->nz * io[k].nrhs * ((io[k].m ? 1 : 0) + (io[k].r ? 1 : 0));
     }
-    bttb_status st = BTTB_OK;
-    if (!fwd.empty()) st = run_forward<T>(fwd, s);
-    // a problem with both products reuses its workspace: the transpose of the
-    // batch runs after every forward (stream order)
-    if (st == BTTB_OK && !tr.empty()) st = run_transpose<T>(tr, s);
+    std::sort(groups.begin(), groups.end(), [](const Group& a, const Group& b) { return a.work > b.work; });
+    std::vector<size_t> branch[kBatchBranches];
+    double load[kBatchBranches] = {};
+    for (const Group& g : groups) {
+        const int b = (int)(std::min_element(load, load + kBatchBranches) - load);
+        load[b] += g.work;
+        branch[b].insert(branch[b].end(), g.idx.begin(), g.idx.end());
+    }
+    int used = 0;
+    for (int b = 0; b < kBatchBranches; ++b) used += !branch[b].empty();
+    auto enqueue = [&](const std::vector<size_t>& ks, hipStream_t st) {
+        std::vector<Item> fwd, tr;
+        for (size_t k : ks) {
+            const bttb_plan_s* P = B->plans[k];
+            char* w = ws + B->ws_off[k];
+            if (io[k].m) fwd.push_back(Item{P, (const char*)io[k].spectra, io[k].m, io[k].d, io[k].nrhs, w});
+            if (io[k].r) tr.push_back(Item{P, (const char*)io[k].spectra, io[k].r, io[k].mt, io[k].nrhs, w});
+        }
+        bttb_status r = BTTB_OK;
+        if (!fwd.empty()) r = run_forward<T>(fwd, st);
+        if (r == BTTB_OK && !tr.empty()) r = run_transpose<T>(tr, st);
+        return r;
+    };
+    if (used <= 1) {
+        for (int b = 0; b < kBatchBranches; ++b)
+            if (!branch[b].empty()) return enqueue(branch[b], s);
+        return BTTB_OK;
+    }
+    bttb_status st = hip_check(hipEventRecord(B->ev[0], s), "fork");
+    for (int b = 0; b < kBatchBranches && st == BTTB_OK; ++b) {
+        if (branch[b].empty()) continue;
+        st = hip_check(hipStreamWaitEvent(B->side[b], B->ev[0], 0), "fork");
+        if (st == BTTB_OK) st = enqueue(branch[b], B->side[b]);
+        if (st == BTTB_OK) st = hip_check(hipEventRecord(B->ev[1 + b], B->side[b]), "join");
+        if (st == BTTB_OK) st = hip_check(hipStreamWaitEvent(s, B->ev[1 + b], 0), "join");
+    }
     return st;
 }
 
@@ -891,7 +937,11 @@ bttb_status bttb_batch_create(const bttb_plan_t* plans, int32_t nplans, int32_t 
         }
         B->fp64 = plans[0]->fp64;
         bttb_status st = hip_check(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking), "stream create");
-        if (st != BTTB_OK) { delete B; return st; }
+        for (int b = 0; b < kBatchBranches && st == BTTB_OK; ++b)
+            st = hip_check(hipStreamCreateWithFlags(&B->side[b], hipStreamNonBlocking), "stream create");
+        for (int b = 0; b <= kBatchBranches && st == BTTB_OK; ++b)
+            st = hip_check(hipEventCreateWithFlags(&B->ev[b], hipEventDisableTiming), "event create");
+        if (st != BTTB_OK) { bttb_batch_destroy(B); return st; }
         *out = B;
         return BTTB_OK;
     } catch (...) {
@@ -957,6 +1007,10 @@ bttb_status bttb_batch_destroy(bttb_batch_t B)
     if (!B) return BTTB_OK;
     batch_release_graph(B);
     if (B->cap) (void)hipStreamDestroy(B->cap);
+    for (int b = 0; b < kBatchBranches; ++b)
+        if (B->side[b]) (void)hipStreamDestroy(B->side[b]);
+    for (int b = 0; b <= kBatchBranches; ++b)
+        if (B->ev[b]) (void)hipEventDestroy(B->ev[b]);
     delete B;
     return BTTB_OK;
 }

@@ -310,23 +310,33 @@ class Batch:
                 pass
             self.handle = None
 
-    def run(self, ms=None, rs=None, stream=None):
+    def run(self, ms=None, rs=None, stream=None, out_ds=None, out_mts=None):
+        """Outputs are new tensors unless out_ds / out_mts (lists matching ms /
+        rs) are given; with the same input and output tensors every call
+        replays the captured graph."""
         n = len(self.plans)
         ms = list(ms) if ms is not None else [None] * n
         rs = list(rs) if rs is not None else [None] * n
+        out_ds = list(out_ds) if out_ds is not None else [None] * n
+        out_mts = list(out_mts) if out_mts is not None else [None] * n
         io, ds, mts = [], [], []
-        for p, m, r in zip(self.plans, ms, rs):
+        for p, m, r, od, omt in zip(self.plans, ms, rs, out_ds, out_mts):
             nr = 1
             d = mt = None
             if m is not None:
                 nr = p._check_vec(m, (p.nz, p.ny, p.nx), "m")
-                d = torch.empty(m.shape[:-3] + (p.sy, p.sx), dtype=p.dtype, device=m.device)
+                d = od if od is not None else torch.empty(m.shape[:-3] + (p.sy, p.sx), dtype=p.dtype, device=m.device)
+                if p._check_vec(d, (p.sy, p.sx), "d") != nr:
+                    raise ValueError("output d has the wrong number of right-hand sides")
             if r is not None:
                 nr2 = p._check_vec(r, (p.sy, p.sx), "r")
                 if m is not None and nr2 != nr:
                     raise ValueError("m and r of one problem need the same number of right-hand sides")
                 nr = nr2
-                mt = torch.empty(r.shape[:-2] + (p.nz, p.ny, p.nx), dtype=p.dtype, device=r.device)
+                mt = omt if omt is not None else torch.empty(r.shape[:-2] + (p.nz, p.ny, p.nx), dtype=p.dtype,
+                                                             device=r.device)
+                if p._check_vec(mt, (p.nz, p.ny, p.nx), "mt") != nr:
+                    raise ValueError("output mt has the wrong number of right-hand sides")
             io.append(_lib.BatchIO(p.spectra.data_ptr(), m.data_ptr() if m is not None else None,
                                    d.data_ptr() if d is not None else None,
                                    r.data_ptr() if r is not None else None,
