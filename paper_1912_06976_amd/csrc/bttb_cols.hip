@@ -160,13 +160,16 @@ k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
     constexpr int TPL = C::TPL;
     constexpr int LL = lds_line_elems(N);
     __shared__ cT<T> lds[(C::CPW + 1) * LL];
-    const ColJob& J = jobs.j[find_job(jobs, blockIdx.x)];
+    // XCD-ordered block index: neighbouring column blocks, whose panel
+    // segments share 128-byte lines, run on one XCD and share its L2
+    const int bid = xcd_order(blockIdx.x, gridDim.x);
+    const ColJob& J = jobs.j[find_job(jobs, bid)];
     const cT<T>* __restrict__ X = (const cT<T>*)J.a;
     const cT<T>* __restrict__ spec = (const cT<T>*)J.spec;
     cT<T>* __restrict__ Y = (cT<T>*)J.b;
     const int64_t ldx = J.lda, ldy = J.ldb;
     const int ny = J.na, sy = J.nb, nz = J.nl, ncols = J.ncols, nrhs = J.nrhs;
-    const int lb = blockIdx.x - J.begin, cb = lb % J.nbx;
+    const int lb = bid - J.begin, cb = lb % J.nbx;
     const int cl = threadIdx.x / TPL, t = threadIdx.x % TPL;
     const int col = cb * C::CPW + cl;
     const int q0 = (lb / J.nbx) * NR;
@@ -309,7 +312,10 @@ k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
     LineTwiddles<T, N> twl;
     twl.load(tw, t);
     const int64_t U = jobs.total, G = gridDim.x;
-    const int u0 = (int)((int64_t)blockIdx.x * U / G), u1 = (int)((int64_t)(blockIdx.x + 1) * U / G);
+    // XCD-ordered: blocks with neighbouring unit ranges (neighbouring column
+    // blocks, whose panel segments share 128-byte lines) run on one XCD
+    const int w = xcd_order(blockIdx.x, (int)G);
+    const int u0 = (int)((int64_t)w * U / G), u1 = (int)((int64_t)(w + 1) * U / G);
     // unit u -> (job k, key = q * nbx + cb, layer l)
     auto decode = [&](int u, int& k, int& key, int& l) {
         k = find_job(jobs, u);
