@@ -67,6 +67,9 @@ typedef enum {
     BTTB_GRAVITY_GZ = 0,   /* vertical gravity, mGal per (g/cm^3) (Sec. 4.1)           */
     BTTB_MAGNETIC_TMI = 1, /* total-field anomaly of induced magnetisation, nT per SI
                               susceptibility (Sec. 4.2)                                */
+    BTTB_USER_TABLE = 2,   /* any spatially invariant kernel: the caller supplies
+                              the entries per layer and cell offset
+                              (bttb_kernel_generate_table; Sec. 1 (vi))           */
     BTTB_PROBE = 99        /* test hook: entry = dx + 4096 dy + 2^24 r for the cell
                               offsets dx = p - pxl - i, dy = q - pyl - j               */
 } bttb_problem;
@@ -89,7 +92,9 @@ typedef enum { BTTB_ACC_DEFAULT = 0, BTTB_ACC_PLAIN = 1, BTTB_ACC_TWOSUM = 2, BT
  *   real values per layer, holds all of it; the paddings become a phase
  *   applied once per column.  Needs N_x >= 2 (s_x - 1 + max(pxl, pxr)) + 1
  *   and the same in y (always true for equal paddings on both sides).
- * BTTB_SPECTRUM_AUTO: REAL_EVEN where it applies, else COMPLEX.
+ * BTTB_SPECTRUM_AUTO: REAL_EVEN where it applies (the gravity kernel), else
+ *   COMPLEX.  A BTTB_USER_TABLE plan uses REAL_EVEN only when asked for (the
+ *   caller declares the table even).
  * The results of both forms agree to rounding. */
 typedef enum { BTTB_SPECTRUM_AUTO = 0, BTTB_SPECTRUM_COMPLEX = 1, BTTB_SPECTRUM_REAL_EVEN = 2 } bttb_spectrum_form;
 
@@ -162,6 +167,23 @@ bttb_status bttb_plan_spectrum_form(bttb_plan_t plan, int32_t* form);
  * workspace: device, >= workspace_bytes of bttb_plan_query(plan, 1, ...). */
 bttb_status bttb_kernel_generate(bttb_plan_t plan, void* spectra, void* workspace,
                                  size_t ws_bytes, void* stream);
+
+/* Fill the spectra of a BTTB_USER_TABLE plan from the caller's entries (the
+ * paper's software takes the kernel's matrix entries from the user, Sec. 1
+ * (vi); the entries depend on the cell offsets only, Sec. 2.1).
+ * table: device, FP64, [nz][wy][wx] with wx = sx + nx - 1, wy = sy + ny - 1:
+ * table[r][dy + sy - 1 + pyl][dx + sx - 1 + pxl] is the entry of G for a
+ * station and a prism of layer r offset by dx = p - pxl - i in
+ * [-(sx - 1 + pxl), nx - 1 - pxl] and dy = q - pyl - j likewise; the plan's
+ * scale (default 1) multiplies it.  With spectrum_form
+ * BTTB_SPECTRUM_REAL_EVEN the caller declares the kernel even,
+ * h_r(dx, dy) = h_r(|dx|, |dy|) (the centred generator then reads, for an
+ * offset outside the table on one side, its mirror).  Other arguments as for
+ * bttb_kernel_generate.  Errors: NULL_POINTER, INVALID_VALUE (not a
+ * BTTB_USER_TABLE plan; bttb_kernel_generate rejects those), WORKSPACE_TOO_SMALL,
+ * HIP. */
+bttb_status bttb_kernel_generate_table(bttb_plan_t plan, const double* table, void* spectra, void* workspace,
+                                       size_t ws_bytes, void* stream);
 
 /* d = G m for nrhs right-hand sides (the paper's mult_BTTB with t = 1).
  * m: device [nrhs][nz][ny][nx]; d: device [nrhs][sy][sx]; workspace >=
@@ -285,7 +307,7 @@ bttb_status bttb_transpose_profiled(bttb_plan_t plan, const void* spectra, const
 /* Test hook: evaluate the FP64 circulant generator T_r of one layer into the
  * workspace and copy it to host_out ([ny_fft][nx_fft] doubles, x fastest).
  * Synchronises the stream.  Errors: NULL_POINTER, INVALID_VALUE (layer out
- * of range), WORKSPACE_TOO_SMALL, HIP. */
+ * of range, or a BTTB_USER_TABLE plan), WORKSPACE_TOO_SMALL, HIP. */
 bttb_status bttb_debug_generator(bttb_plan_t plan, int32_t layer, double* host_out,
                                  void* workspace, size_t ws_bytes, void* stream);
 

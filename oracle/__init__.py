@@ -17,7 +17,9 @@ eq. continuousforwardmodel / eq. Gslice of Hogue, Renaut & Vatankhah):
 * ``station_sums`` / ``prism_sums`` -- single rows / columns of G m and G^T r
                       for volumes too large for a dense G;
 * ``regularized_lsq`` -- the minimiser of ||G m - d||^2 + lam^2 ||m||^2 from
-                      the dense normal equations (checks the inversion driver).
+                      the dense normal equations (checks the inversion driver);
+* ``dense_from_table`` -- dense G of a kernel given by its entries per layer
+                      and cell offset (checks user-supplied kernels).
 
 The magnetic kernel is the total-field anomaly of induced magnetisation
 (Sec. 4.2); the gravity kernel is g_z (Sec. 4.1).  Conventions (0-based):
@@ -283,3 +285,17 @@ def regularized_lsq(G: np.ndarray, d: np.ndarray, lam: float) -> np.ndarray:
     G = np.asarray(G, dtype=np.float64)
     A = G.T @ G + lam * lam * np.eye(G.shape[1])
     return np.linalg.solve(A, G.T @ np.asarray(d, dtype=np.float64).ravel())
+
+
+def dense_from_table(pr: dict, table: np.ndarray) -> np.ndarray:
+    """Dense G of a spatially invariant kernel given by its entries per layer
+    and cell offset (Sec. 2.1: an entry depends only on the offsets
+    dx = p - pxl - i, dy = q - pyl - j and the layer r):
+    G[j sx + i, r nx ny + q nx + p] = table[r][dy + sy - 1 + pyl][dx + sx - 1 + pxl]."""
+    sx, sy, nz, pxl, pyl = pr["sx"], pr["sy"], pr["nz"], pr["pxl"], pr["pyl"]
+    nx, ny = sx + pxl + pr["pxr"], sy + pyl + pr["pyr"]
+    t = np.asarray(table, dtype=np.float64).reshape(nz, sy + ny - 1, sx + nx - 1)
+    ix = (np.arange(nx)[None, :] - pxl - np.arange(sx)[:, None]) + sx - 1 + pxl     # [sx, nx]
+    iy = (np.arange(ny)[None, :] - pyl - np.arange(sy)[:, None]) + sy - 1 + pyl     # [sy, ny]
+    g = t[:, iy[:, None, :, None], ix[None, :, None, :]]                             # [nz, sy, sx, ny, nx]
+    return np.ascontiguousarray(g.transpose(1, 2, 0, 3, 4).reshape(sy * sx, nz * ny * nx))

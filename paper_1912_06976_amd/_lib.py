@@ -12,7 +12,7 @@ BTTB_OK = 0
 STATUS_NAMES = {0: "BTTB_OK", 1: "BTTB_ERR_INVALID_VALUE", 2: "BTTB_ERR_NULL_POINTER",
                 3: "BTTB_ERR_UNSUPPORTED", 4: "BTTB_ERR_WORKSPACE_TOO_SMALL", 5: "BTTB_ERR_HIP",
                 6: "BTTB_ERR_INTERNAL"}
-BTTB_GRAVITY_GZ, BTTB_MAGNETIC_TMI, BTTB_PROBE = 0, 1, 99
+BTTB_GRAVITY_GZ, BTTB_MAGNETIC_TMI, BTTB_USER_TABLE, BTTB_PROBE = 0, 1, 2, 99
 BTTB_FP32, BTTB_FP64 = 0, 1
 BTTB_ACC_DEFAULT, BTTB_ACC_PLAIN, BTTB_ACC_TWOSUM, BTTB_ACC_WIDE = 0, 1, 2, 3
 BTTB_SPECTRUM_AUTO, BTTB_SPECTRUM_COMPLEX, BTTB_SPECTRUM_REAL_EVEN = 0, 1, 2
@@ -20,7 +20,7 @@ BTTB_SPECTRUM_AUTO, BTTB_SPECTRUM_COMPLEX, BTTB_SPECTRUM_REAL_EVEN = 0, 1, 2
 #: every symbol include/bttb.h declares
 EXPORTS = ["bttb_plan_create", "bttb_plan_destroy", "bttb_plan_query", "bttb_kernel_generate",
            "bttb_forward", "bttb_transpose", "bttb_forward_profiled", "bttb_transpose_profiled",
-           "bttb_debug_generator", "bttb_plan_spectrum_form", "bttb_cgls_query", "bttb_cgls", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
+           "bttb_debug_generator", "bttb_plan_spectrum_form", "bttb_kernel_generate_table", "bttb_cgls_query", "bttb_cgls", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
            "bttb_batch_destroy", "bttb_autotune_query", "bttb_autotune", "bttb_status_string",
            "bttb_last_error"]
 
@@ -78,6 +78,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     L.bttb_transpose_profiled.argtypes = [vp, vp, vp, vp, i32, vp, sz, vp, ctypes.POINTER(ctypes.c_float)]
     L.bttb_debug_generator.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), vp, sz, vp]
     L.bttb_plan_spectrum_form.argtypes = [vp, ctypes.POINTER(i32)]
+    L.bttb_kernel_generate_table.argtypes = [vp, vp, vp, vp, sz, vp]
     L.bttb_cgls_query.argtypes = [vp, ctypes.POINTER(sz)]
     L.bttb_cgls.argtypes = [vp, vp, vp, vp, ctypes.c_double, i32, vp, vp, sz, vp]
     L.bttb_batch_create.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp)]
@@ -93,7 +94,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     L.bttb_last_error.restype = ctypes.c_char_p
     for name in ["bttb_plan_create", "bttb_plan_destroy", "bttb_plan_query", "bttb_kernel_generate",
                  "bttb_forward", "bttb_transpose", "bttb_forward_profiled", "bttb_transpose_profiled",
-                 "bttb_debug_generator", "bttb_plan_spectrum_form", "bttb_cgls_query", "bttb_cgls", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
+                 "bttb_debug_generator", "bttb_plan_spectrum_form", "bttb_kernel_generate_table", "bttb_cgls_query", "bttb_cgls", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
                  "bttb_batch_destroy", "bttb_autotune_query", "bttb_autotune"]:
         getattr(L, name).restype = ctypes.c_int
     _handle = L

@@ -69,8 +69,10 @@ namespace {
 
 bttb_status validate_and_fill(const bttb_problem_desc* d, bttb_plan_s* P)
 {
-    if (d->problem != BTTB_GRAVITY_GZ && d->problem != BTTB_MAGNETIC_TMI && d->problem != BTTB_PROBE)
-        return fail(BTTB_ERR_INVALID_VALUE, "problem must be BTTB_GRAVITY_GZ, BTTB_MAGNETIC_TMI or BTTB_PROBE");
+    if (d->problem != BTTB_GRAVITY_GZ && d->problem != BTTB_MAGNETIC_TMI && d->problem != BTTB_USER_TABLE &&
+        d->problem != BTTB_PROBE)
+        return fail(BTTB_ERR_INVALID_VALUE,
+                    "problem must be BTTB_GRAVITY_GZ, BTTB_MAGNETIC_TMI, BTTB_USER_TABLE or BTTB_PROBE");
     if (d->precision != BTTB_FP32 && d->precision != BTTB_FP64)
         return fail(BTTB_ERR_INVALID_VALUE, "precision must be BTTB_FP32 or BTTB_FP64");
     if (d->sx < 1 || d->sy < 1 || d->nz < 1)
@@ -174,12 +176,15 @@ bttb_status validate_and_fill(const bttb_problem_desc* d, bttb_plan_s* P)
     // |offset| <= bx and must not wrap: 2 bx + 1 <= Nx
     P->bx = d->sx - 1 + std::max(d->pxl, d->pxr);
     P->by = d->sy - 1 + std::max(d->pyl, d->pyr);
-    const bool even_ok = d->problem == BTTB_GRAVITY_GZ && 2 * (int64_t)P->bx + 1 <= Nx && 2 * (int64_t)P->by + 1 <= Ny;
+    const bool fits = 2 * (int64_t)P->bx + 1 <= Nx && 2 * (int64_t)P->by + 1 <= Ny;
+    const bool even_ok = (d->problem == BTTB_GRAVITY_GZ || d->problem == BTTB_USER_TABLE) && fits;
     if (d->spectrum_form == BTTB_SPECTRUM_REAL_EVEN && !even_ok)
         return fail(BTTB_ERR_UNSUPPORTED,
-                    "BTTB_SPECTRUM_REAL_EVEN needs the gravity kernel and nx_fft >= 2 (sx - 1 + max(pxl, pxr)) + 1, "
-                    "ny_fft >= 2 (sy - 1 + max(pyl, pyr)) + 1");
-    P->form = (even_ok && d->spectrum_form != BTTB_SPECTRUM_COMPLEX) ? FORM_REAL_EVEN : FORM_COMPLEX;
+                    "BTTB_SPECTRUM_REAL_EVEN needs the gravity kernel (or an even user table) and "
+                    "nx_fft >= 2 (sx - 1 + max(pxl, pxr)) + 1, ny_fft >= 2 (sy - 1 + max(pyl, pyr)) + 1");
+    const bool use_even = d->spectrum_form == BTTB_SPECTRUM_REAL_EVEN ||
+                          (d->spectrum_form == BTTB_SPECTRUM_AUTO && d->problem == BTTB_GRAVITY_GZ && fits);
+    P->form = use_even ? FORM_REAL_EVEN : FORM_COMPLEX;
     P->ldr = (Ny / 2 + 1 + 31) / 32 * 32;
     P->off_spec = off;
     const size_t csz = 2 * P->esz;
@@ -229,11 +234,17 @@ bttb_status hip_check(hipError_t e, const char* what)
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
-GenParams gen_params(const bttb_plan_s* P, int r0, int nl)
+GenParams gen_params(const bttb_plan_s* P, int r0, int nl, const double* table = nullptr)
 {
     GenParams g{};
     g.kind = P->d.problem == BTTB_GRAVITY_GZ ? KIND_GRAVITY
-           : P->d.problem == BTTB_MAGNETIC_TMI ? KIND_MAGNETIC : KIND_PROBE;
+           : P->d.problem == BTTB_MAGNETIC_TMI ? KIND_MAGNETIC
+           : P->d.problem == BTTB_USER_TABLE ? KIND_TABLE : KIND_PROBE;
+    g.table = table;
+    g.wx = P->sx + P->nx - 1;
+    g.wy = P->sy + P->ny - 1;
+    g.offx = P->sx - 1 + P->d.pxl;
+    g.offy = P->sy - 1 + P->d.pyl;
     g.sx = P->sx; g.sy = P->sy; g.nx = P->nx; g.ny = P->ny;
     g.pxl = P->d.pxl; g.pyl = P->d.pyl;
     g.Nx = P->Nx; g.Ny = P->Ny;
@@ -247,7 +258,7 @@ GenParams gen_params(const bttb_plan_s* P, int r0, int nl)
 }
 
 template <typename T>
-bttb_status run_generate(const bttb_plan_s* P, char* spec, char* ws, hipStream_t s)
+bttb_status run_generate(const bttb_plan_s* P, char* spec, char* ws, hipStream_t s, const double* table = nullptr)
 {
     double2* tw64x = (double2*)(spec + P->off_tw64x);
     double2* tw64y = (double2*)(spec + P->off_tw64y);
@@ -263,7 +274,7 @@ bttb_status run_generate(const bttb_plan_s* P, char* spec, char* ws, hipStream_t
     const double inv = 1.0 / ((double)P->Nx * (double)P->Ny);
     for (int r0 = 0; r0 < P->nz; r0 += P->gen_batch) {
         const int nl = std::min(P->gen_batch, P->nz - r0);
-        const GenParams g = gen_params(P, r0, nl);
+        const GenParams g = gen_params(P, r0, nl, table);
         if ((st = hip_check(launch_generate(g, r0, nl, g64, s), "generate")) != BTTB_OK) return st;
         RowJobs rj{};
         rj.njobs = 1;
@@ -663,11 +674,35 @@ bttb_status bttb_kernel_generate(bttb_plan_t plan, void* spectra, void* workspac
             return fail(BTTB_ERR_INVALID_VALUE, "spectra must be 256-byte aligned and workspace 16-byte aligned");
         if (ws_bytes < ws_layout(plan, 1).total)
             return fail(BTTB_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than bttb_plan_query(plan, 1) reports");
+        if (plan->d.problem == BTTB_USER_TABLE)
+            return fail(BTTB_ERR_INVALID_VALUE, "a BTTB_USER_TABLE plan takes its entries from bttb_kernel_generate_table");
         hipStream_t s = (hipStream_t)stream;
         return plan->fp64 ? run_generate<double>(plan, (char*)spectra, (char*)workspace, s)
                           : run_generate<float>(plan, (char*)spectra, (char*)workspace, s);
     } catch (...) {
         return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_kernel_generate");
+    }
+}
+
+bttb_status bttb_kernel_generate_table(bttb_plan_t plan, const double* table, void* spectra, void* workspace,
+                                       size_t ws_bytes, void* stream)
+{
+    try {
+        g_last_error.clear();
+        if (!plan || !table || !spectra || !workspace)
+            return fail(BTTB_ERR_NULL_POINTER, "plan, table, spectra and workspace must not be NULL");
+        if (plan->d.problem != BTTB_USER_TABLE)
+            return fail(BTTB_ERR_INVALID_VALUE, "bttb_kernel_generate_table needs a BTTB_USER_TABLE plan");
+        if (!aligned(spectra, kAlign) || !aligned(workspace, 16) || !aligned(table, 8))
+            return fail(BTTB_ERR_INVALID_VALUE,
+                        "spectra must be 256-byte aligned, workspace 16-byte aligned and table 8-byte aligned");
+        if (ws_bytes < ws_layout(plan, 1).total)
+            return fail(BTTB_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than bttb_plan_query(plan, 1) reports");
+        hipStream_t s = (hipStream_t)stream;
+        return plan->fp64 ? run_generate<double>(plan, (char*)spectra, (char*)workspace, s, table)
+                          : run_generate<float>(plan, (char*)spectra, (char*)workspace, s, table);
+    } catch (...) {
+        return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_kernel_generate_table");
     }
 }
 
@@ -810,6 +845,8 @@ bttb_status bttb_debug_generator(bttb_plan_t plan, int32_t layer, double* host_o
         if (ws_bytes < need || ws_bytes < ws_layout(plan, 1).total)
             return fail(BTTB_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than bttb_plan_query(plan, 1) reports");
         if (!aligned(workspace, 16)) return fail(BTTB_ERR_INVALID_VALUE, "workspace must be 16-byte aligned");
+        if (plan->d.problem == BTTB_USER_TABLE)
+            return fail(BTTB_ERR_INVALID_VALUE, "bttb_debug_generator does not take BTTB_USER_TABLE plans");
         hipStream_t s = (hipStream_t)stream;
         const GenParams g = gen_params(plan, layer, 1);
         bttb_status st = hip_check(launch_generate(g, layer, 1, (double*)workspace, s), "generate");
@@ -1136,8 +1173,21 @@ bttb_status bttb_autotune(const bttb_problem_desc* desc, int32_t nrhs, void* scr
         char* base_ptr = (char*)scratch;
         char* spec = base_ptr + L.spec;
         char* ws = base_ptr + L.ws;
-        // spectra do not depend on the tuning choices: generate once
-        st = base.fp64 ? run_generate<double>(&base, spec, ws, s) : run_generate<float>(&base, spec, ws, s);
+        // spectra do not depend on the tuning choices: generate once (a user
+        // table plan has no entries here; its timing does not depend on the
+        // values, so its spectra are zeros)
+        if (base.d.problem == BTTB_USER_TABLE) {
+            st = hip_check(hipMemsetAsync(spec, 0, base.spec_bytes, s), "memset");
+            if (st == BTTB_OK)
+                st = hip_check(launch_twiddles((double2*)(spec + base.off_tw64x),
+                                               base.fp64 ? nullptr : (float2*)(spec + base.off_twx), base.Nx, s),
+                               "twiddles x");
+            if (st == BTTB_OK)
+                st = hip_check(launch_twiddles((double2*)(spec + base.off_tw64y),
+                                               base.fp64 ? nullptr : (float2*)(spec + base.off_twy), base.Ny, s),
+                               "twiddles y");
+        } else
+            st = base.fp64 ? run_generate<double>(&base, spec, ws, s) : run_generate<float>(&base, spec, ws, s);
         if (st != BTTB_OK) return st;
         if ((st = hip_check(hipMemsetAsync(base_ptr + L.m, 0, L.d - L.m, s), "memset")) != BTTB_OK) return st;
         if ((st = hip_check(hipMemsetAsync(base_ptr + L.r, 0, L.mt - L.r, s), "memset")) != BTTB_OK) return st;

@@ -5,7 +5,7 @@
 
 namespace bttbk {
 
-enum { KIND_GRAVITY = 0, KIND_MAGNETIC = 1, KIND_PROBE = 99 };
+enum { KIND_GRAVITY = 0, KIND_MAGNETIC = 1, KIND_TABLE = 2, KIND_PROBE = 99 };
 enum { ACC_PLAIN = 0, ACC_TWOSUM = 1, ACC_WIDE = 2 };
 // stored spectrum forms (see bttb_cols.hip)
 enum { FORM_COMPLEX = 0, FORM_REAL_EVEN = 1 };
@@ -25,6 +25,10 @@ struct GenParams {
     // centred even placement (real even spectra): T[ay][ax] = h(|ax|, |ay|)
     // for |ax| <= bx, |ay| <= by
     int sym, bx, by;
+    // KIND_TABLE: caller's entries [nz][wy][wx], offset (dx, dy) at
+    // [dy + offy][dx + offx]
+    const double* table;
+    int wx, wy, offx, offy;
 };
 
 // Half spectra along x (packed: N/2 columns) of a block of R rows are stored

@@ -101,6 +101,13 @@ __global__ void k_generate(GenParams P, int r0, double* __restrict__ out)
     if (inside) {
         if (P.kind == KIND_PROBE) {
             val = (double)ox + 4096.0 * (double)oy + 16777216.0 * (double)r;
+        } else if (P.kind == KIND_TABLE) {
+            // the caller's entry; the centred placement of an even kernel
+            // reads the mirror of an offset the table has on one side only
+            int tx = ox + P.offx, ty = oy + P.offy;
+            if (tx >= P.wx) tx = P.offx - ox;
+            if (ty >= P.wy) ty = P.offy - oy;
+            val = P.scale * P.table[((int64_t)r * P.wy + ty) * P.wx + tx];
         } else {
             const double x1 = ((double)ox - 0.5) * P.dx, x2 = ((double)ox + 0.5) * P.dx;
             const double y1 = ((double)oy - 0.5) * P.dy, y2 = ((double)oy + 0.5) * P.dy;

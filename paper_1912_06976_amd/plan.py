@@ -16,7 +16,8 @@ import torch
 from . import _lib
 from ._lib import check
 
-_KIND = {"gravity": _lib.BTTB_GRAVITY_GZ, "magnetic": _lib.BTTB_MAGNETIC_TMI, "probe": _lib.BTTB_PROBE}
+_KIND = {"gravity": _lib.BTTB_GRAVITY_GZ, "magnetic": _lib.BTTB_MAGNETIC_TMI, "table": _lib.BTTB_USER_TABLE,
+         "probe": _lib.BTTB_PROBE}
 _PREC = {"fp32": _lib.BTTB_FP32, "fp64": _lib.BTTB_FP64}
 _FORM = {"auto": _lib.BTTB_SPECTRUM_AUTO, "complex": _lib.BTTB_SPECTRUM_COMPLEX,
          "real_even": _lib.BTTB_SPECTRUM_REAL_EVEN}
@@ -92,6 +93,19 @@ def bttb_kernel_generate(plan: int, spectra: torch.Tensor, workspace: torch.Tens
           _lib.load().bttb_kernel_generate(ctypes.c_void_p(plan), _ptr(spectra), _ptr(workspace),
                                            workspace.numel() * workspace.element_size(),
                                            _stream_ptr(stream)))
+
+
+def bttb_kernel_generate_table(plan: int, table: torch.Tensor, spectra: torch.Tensor, workspace: torch.Tensor,
+                               stream=None) -> None:
+    """Spectra of a "table" plan from the caller's entries: table is a
+    contiguous float64 device tensor [nz, sy + ny - 1, sx + nx - 1] indexed by
+    the cell offsets (dy + sy - 1 + pyl, dx + sx - 1 + pxl)."""
+    if table.device.type != "cuda" or table.dtype != torch.float64 or not table.is_contiguous():
+        raise ValueError("table must be a contiguous float64 CUDA tensor")
+    check("bttb_kernel_generate_table",
+          _lib.load().bttb_kernel_generate_table(ctypes.c_void_p(plan), _ptr(table), _ptr(spectra), _ptr(workspace),
+                                                 workspace.numel() * workspace.element_size(),
+                                                 _stream_ptr(stream)))
 
 
 def bttb_forward(plan: int, spectra: torch.Tensor, m: torch.Tensor, d: torch.Tensor, nrhs: int,
@@ -201,10 +215,21 @@ class Plan:
         return self._ws
 
     # -- operations ---------------------------------------------------------
-    def generate(self, stream=None) -> "Plan":
+    def generate(self, table: torch.Tensor | None = None, stream=None) -> "Plan":
+        """Fill the spectra: from the closed-form kernel, or (a "table" plan)
+        from the caller's entries, [nz, sy + ny - 1, sx + nx - 1] float64 on
+        the device, indexed by the cell offsets."""
         if self.spectra is None:
             self.spectra = torch.empty(self.spectra_bytes, dtype=torch.uint8, device=self.device)
-        bttb_kernel_generate(self.handle, self.spectra, self.workspace(1), stream)
+        if self.problem["kind"] == "table":
+            if table is None:
+                raise ValueError("a table plan needs its entries: generate(table=...)")
+            want = (self.nz, self.sy + self.ny - 1, self.sx + self.nx - 1)
+            if tuple(table.shape) != want:
+                raise ValueError("table has shape %s, expected %s" % (tuple(table.shape), want))
+            bttb_kernel_generate_table(self.handle, table.contiguous(), self.spectra, self.workspace(1), stream)
+        else:
+            bttb_kernel_generate(self.handle, self.spectra, self.workspace(1), stream)
         return self
 
     def _check_vec(self, t: torch.Tensor, tail, name):

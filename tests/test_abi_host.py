@@ -56,7 +56,7 @@ def _create(prob, prec="fp32", **over):
 
 @pytest.mark.parametrize("field,value,status", [
     ("sx", 0, 1), ("sy", -3, 1), ("nz", 0, 1), ("pxl", -1, 1), ("dx", 0.0, 1), ("dy", float("nan"), 1),
-    ("dz", -1.0, 1), ("station_height", -1.0, 1), ("problem", 7, 1), ("precision", 3, 1),
+    ("dz", -1.0, 1), ("station_height", -1.0, 1), ("problem", 7, 1), ("problem", 3, 1), ("precision", 3, 1),
     ("nx", 17, 1), ("nx_fft", 16, 1), ("nx_fft", 96, 3), ("ny_fft", 8192, 3), ("accumulation", 9, 1),
     ("layer_chunk", -1, 1), ("row_tile", 3, 1), ("col_tile", 4, 1), ("spectrum_form", 3, 1),
 ])
@@ -142,10 +142,33 @@ def test_spectrum_form_choice(lib):
         h = B.bttb_plan_create(dict(pr, spectrum_form=req), "fp32")
         assert B.bttb_plan_spectrum_form(h) == got, (pr, req)
         B.bttb_plan_destroy(h)
-    for pr in (W.magnetic_48x56(), W.problem(W.GRAVITY, 5, 5, 2, 6, 0, 0, 0, dx=10.0, dy=10.0, dz=5.0)):
+    for pr in (W.magnetic_48x56(), W.problem(W.GRAVITY, 5, 5, 2, 6, 0, 0, 0, dx=10.0, dy=10.0, dz=5.0),
+               W.problem(W.TABLE, 5, 5, 2, 6, 0, 0, 0)):
         st, h, msg = _create(dict(pr, spectrum_form="real_even"))
         assert st == 3 and h.value is None and "REAL_EVEN" in msg
+    # a user table is complex unless declared even
+    for req, got in (("auto", "complex"), ("real_even", "real_even")):
+        h = B.bttb_plan_create(dict(W.problem(W.TABLE, 13, 11, 5, 0, 3, 4, 1), spectrum_form=req), "fp32")
+        assert B.bttb_plan_spectrum_form(h) == got
+        B.bttb_plan_destroy(h)
     assert lib.bttb_plan_spectrum_form(None, None) == 2
+
+
+def test_table_generation_argument_checks(lib):
+    # fake (never dereferenced) device pointers: the checks fail first
+    import paper_1912_06976_amd as B
+    h = B.bttb_plan_create(W.problem(W.TABLE, 13, 11, 5, 0, 3, 4, 1), "fp64")
+    g = B.bttb_plan_create(W.small_gravity(), "fp64")
+    _, wb, _, _ = B.bttb_plan_query(h, 1)
+    p = ctypes.c_void_p(1 << 20)
+    assert lib.bttb_kernel_generate_table(ctypes.c_void_p(h), None, p, p, wb, None) == 2
+    assert lib.bttb_kernel_generate_table(ctypes.c_void_p(g), p, p, p, wb, None) == 1
+    assert lib.bttb_kernel_generate(ctypes.c_void_p(h), p, p, wb, None) == 1
+    assert lib.bttb_kernel_generate_table(ctypes.c_void_p(h), p, p, p, wb - 1, None) == 4
+    host = (ctypes.c_double * 4)()
+    assert lib.bttb_debug_generator(ctypes.c_void_p(h), 0, host, p, 1 << 30, None) == 1
+    B.bttb_plan_destroy(h)
+    B.bttb_plan_destroy(g)
 
 
 def test_workspace_too_small_is_rejected_before_launch(lib):

@@ -474,3 +474,15 @@ def test_regularized_lsq_matches_svd_filter_factors_and_augmented_lstsq(oracle_l
     m = oracle.regularized_lsq(G, d, lam)
     ref = G.T @ d / lam ** 2
     assert np.linalg.norm(m - ref) <= 1e-6 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("pr", [W.small_gravity(), W.magnetic_48x56(),
+                                W.problem(W.MAGNETIC, 9, 6, 3, 1, 2, 2, 1, dx=50.0, dy=100.0, dz=30.0,
+                                          h=7.0, incl=-30.0, decl=140.0, field_nT=52000.0)])
+def test_dense_from_table_reproduces_geometry_entries(oracle_lib, pr):
+    # the offsets table of the exact entries, indexed by cell offset, gives
+    # back the matrix assembled from the station and prism coordinates
+    import oracle
+    P = oracle.problem_from_dict(pr)
+    t, _ = oracle.offset_table_quad(P)
+    assert np.array_equal(oracle.dense_from_table(pr, t), oracle.dense_G_quad(P))

@@ -24,7 +24,7 @@ import math
 
 import numpy as np
 
-GRAVITY, MAGNETIC, PROBE = "gravity", "magnetic", "probe"
+GRAVITY, MAGNETIC, TABLE, PROBE = "gravity", "magnetic", "table", "probe"
 
 
 def problem(kind, sx, sy, nz, pxl=0, pxr=0, pyl=0, pyr=0, dx=1.0, dy=1.0, dz=1.0,
