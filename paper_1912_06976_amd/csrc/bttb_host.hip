@@ -63,6 +63,8 @@ struct bttb_plan_s {
     int form;                    // FORM_COMPLEX or FORM_REAL_EVEN
     int64_t ldr;                 // real even spectra: line stride (elements)
     int bx, by;                  // real even spectra: largest |offset| used in x and y
+    int oxmin, oymin, cx, cy;    // corner grid of the generator (offsets of its first
+                                 // corner, corners per row / column)
 };
 
 namespace {
@@ -185,6 +187,12 @@ bttb_status validate_and_fill(const bttb_problem_desc* d, bttb_plan_s* P)
     const bool use_even = d->spectrum_form == BTTB_SPECTRUM_REAL_EVEN ||
                           (d->spectrum_form == BTTB_SPECTRUM_AUTO && d->problem == BTTB_GRAVITY_GZ && fits);
     P->form = use_even ? FORM_REAL_EVEN : FORM_COMPLEX;
+    // corner grid: the entries' offsets are [-(sx - 1 + pxl), nx - 1 - pxl]
+    // (centred placement: [0, bx]); one more corner than entries per axis
+    P->oxmin = use_even ? 0 : -(d->sx - 1 + d->pxl);
+    P->oymin = use_even ? 0 : -(d->sy - 1 + d->pyl);
+    P->cx = use_even ? P->bx + 2 : (int)(d->sx + nx);
+    P->cy = use_even ? P->by + 2 : (int)(d->sy + ny);
     P->ldr = (Ny / 2 + 1 + 31) / 32 * 32;
     P->off_spec = off;
     const size_t csz = 2 * P->esz;
@@ -201,7 +209,7 @@ bttb_status validate_and_fill(const bttb_problem_desc* d, bttb_plan_s* P)
 }
 
 struct WsLayout {
-    size_t gen_a, gen_b, gen_total;
+    size_t gen_a, gen_b, gen_c, gen_total;
     size_t fwd_x, fwd_y, fwd_total;
     size_t tr_r, tr_z, tr_total;
     size_t total;
@@ -213,7 +221,8 @@ WsLayout ws_layout(const bttb_plan_s* P, int nrhs)
     const size_t csz = 2 * P->esz;
     L.gen_a = 0;
     L.gen_b = align_up((size_t)P->gen_batch * P->Nx * (size_t)P->Ny * 8);
-    L.gen_total = align_up(L.gen_b + (size_t)P->gen_batch * P->ncols * (size_t)P->Ny * 16);
+    L.gen_c = align_up(L.gen_b + (size_t)P->gen_batch * P->ncols * (size_t)P->Ny * 16);
+    L.gen_total = align_up(L.gen_c + (size_t)(P->gen_batch + 1) * P->cx * (size_t)P->cy * 8);
     // half spectra in panels: ncols * panel_rows(rows) per block
     const size_t pny = (size_t)panel_rows(P->ny), psy = (size_t)panel_rows(P->sy);
     L.fwd_x = 0;
@@ -234,9 +243,15 @@ bttb_status hip_check(hipError_t e, const char* what)
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
-GenParams gen_params(const bttb_plan_s* P, int r0, int nl, const double* table = nullptr)
+GenParams gen_params(const bttb_plan_s* P, int r0, int nl, const double* table = nullptr,
+                     const double* corners = nullptr)
 {
     GenParams g{};
+    g.corners = corners;
+    g.oxmin = P->oxmin;
+    g.oymin = P->oymin;
+    g.cx = P->cx;
+    g.cy = P->cy;
     g.kind = P->d.problem == BTTB_GRAVITY_GZ ? KIND_GRAVITY
            : P->d.problem == BTTB_MAGNETIC_TMI ? KIND_MAGNETIC
            : P->d.problem == BTTB_USER_TABLE ? KIND_TABLE : KIND_PROBE;
@@ -270,11 +285,14 @@ bttb_status run_generate(const bttb_plan_s* P, char* spec, char* ws, hipStream_t
     const WsLayout L = ws_layout(P, 1);
     double* g64 = (double*)(ws + L.gen_a);
     double2* w64 = (double2*)(ws + L.gen_b);
+    double* corners = (double*)(ws + L.gen_c);
+    const bool closed_form = P->d.problem == BTTB_GRAVITY_GZ || P->d.problem == BTTB_MAGNETIC_TMI;
     void* out = spec + P->off_spec;
     const double inv = 1.0 / ((double)P->Nx * (double)P->Ny);
     for (int r0 = 0; r0 < P->nz; r0 += P->gen_batch) {
         const int nl = std::min(P->gen_batch, P->nz - r0);
-        const GenParams g = gen_params(P, r0, nl, table);
+        const GenParams g = gen_params(P, r0, nl, table, corners);
+        if (closed_form && (st = hip_check(launch_corners(g, nl, corners, s), "corners")) != BTTB_OK) return st;
         if ((st = hip_check(launch_generate(g, r0, nl, g64, s), "generate")) != BTTB_OK) return st;
         RowJobs rj{};
         rj.njobs = 1;
@@ -848,8 +866,12 @@ bttb_status bttb_debug_generator(bttb_plan_t plan, int32_t layer, double* host_o
         if (plan->d.problem == BTTB_USER_TABLE)
             return fail(BTTB_ERR_INVALID_VALUE, "bttb_debug_generator does not take BTTB_USER_TABLE plans");
         hipStream_t s = (hipStream_t)stream;
-        const GenParams g = gen_params(plan, layer, 1);
-        bttb_status st = hip_check(launch_generate(g, layer, 1, (double*)workspace, s), "generate");
+        double* corners = (double*)((char*)workspace + ws_layout(plan, 1).gen_c);
+        const GenParams g = gen_params(plan, layer, 1, nullptr, corners);
+        bttb_status st = BTTB_OK;
+        if (plan->d.problem == BTTB_GRAVITY_GZ || plan->d.problem == BTTB_MAGNETIC_TMI)
+            st = hip_check(launch_corners(g, 1, corners, s), "corners");
+        if (st == BTTB_OK) st = hip_check(launch_generate(g, layer, 1, (double*)workspace, s), "generate");
         if (st != BTTB_OK) return st;
         if ((st = hip_check(hipMemcpyAsync(host_out, workspace, need, hipMemcpyDeviceToHost, s), "copy")) != BTTB_OK)
             return st;

@@ -29,6 +29,11 @@ struct GenParams {
     // [dy + offy][dx + offx]
     const double* table;
     int wx, wy, offx, offy;
+    // gravity / magnetic: the corner grid of the batch, cy x cx corner terms
+    // per depth edge z_{r0} .. z_{r0 + nl}; corner (ex, ey) at
+    // x = (oxmin + ex - 1/2) dx, y = (oymin + ey - 1/2) dy
+    const double* corners;
+    int oxmin, oymin, cx, cy;
 };
 
 // Half spectra along x (packed: N/2 columns) of a block of R rows are stored
@@ -93,6 +98,9 @@ template <> struct cplx<double> { using type = double2; };
 template <typename T> using cT = typename cplx<T>::type;
 
 hipError_t launch_twiddles(double2* t64, float2* t32, int n, hipStream_t s);
+// corner grid of the depth edges z_{r0} .. z_{r0 + nl} into P.corners
+// (gravity / magnetic), then the generator of layers [r0, r0 + nl)
+hipError_t launch_corners(const GenParams& P, int nl, double* corners, hipStream_t s);
 hipError_t launch_generate(const GenParams& P, int r0, int nl, double* out, hipStream_t s);
 // rows per row group (row tile 2 or 4 pairs) and columns per column block
 // (column tile 1 or 2 times the default) of the kernels for length N

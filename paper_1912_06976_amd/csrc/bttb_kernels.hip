@@ -68,6 +68,24 @@ __device__ __forceinline__ double corner_tmi(double x, double y, double z, const
     return f;
 }
 
+// Corner grid (the paper's gravity / magnetic algorithms evaluate the
+// closed form once per corner of the grid of prism edges, Sec. 4.1 / 4.2):
+// one thread per corner (ex, ey) of depth edge k = blockIdx.y of the batch,
+// F[k][ey][ex] = f((oxmin + ex - 1/2) dx, (oymin + ey - 1/2) dy, z_k + h).
+// Each value is shared by the four entries whose prisms meet at that corner
+// and by the two layers on either side of the edge.
+__global__ void k_corners(GenParams P, double* __restrict__ F)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)P.cx * P.cy;
+    if (idx >= per) return;
+    const int ex = (int)(idx % P.cx), ey = (int)(idx / P.cx);
+    const double x = ((double)(P.oxmin + ex) - 0.5) * P.dx;
+    const double y = ((double)(P.oymin + ey) - 0.5) * P.dy;
+    const double z = P.z[blockIdx.y] + P.h;
+    F[(int64_t)blockIdx.y * per + idx] = P.kind == KIND_GRAVITY ? corner_gz(x, y, z) : corner_tmi(x, y, z, P.w);
+}
+
 // One thread per circulant position (X, Y) of layer r = r0 + blockIdx.y:
 //   T_r[Y][X] = h_r(-ax - pxl, -ay - pyl) if ax in [-(nx-1), sx-1] and
 //   ay in [-(ny-1), sy-1], with ax = X or X - Nx (and likewise ay), else 0.
@@ -109,10 +127,10 @@ __global__ void k_generate(GenParams P, int r0, double* __restrict__ out)
             if (ty >= P.wy) ty = P.offy - oy;
             val = P.scale * P.table[((int64_t)r * P.wy + ty) * P.wx + tx];
         } else {
-            const double x1 = ((double)ox - 0.5) * P.dx, x2 = ((double)ox + 0.5) * P.dx;
-            const double y1 = ((double)oy - 0.5) * P.dy, y2 = ((double)oy + 0.5) * P.dy;
-            const double z1 = P.z[blockIdx.y] + P.h, z2 = P.z[blockIdx.y + 1] + P.h;
-            const double xs[2] = {x1, x2}, ys[2] = {y1, y2}, zs[2] = {z1, z2};
+            // signed sum of the 8 corner terms of the prism (corner grid of
+            // the batch, edges blockIdx.y and blockIdx.y + 1)
+            const int64_t per = (int64_t)P.cx * P.cy;
+            const double* F = P.corners + (int64_t)blockIdx.y * per + (int64_t)(oy - P.oymin) * P.cx + (ox - P.oxmin);
             double s = 0.0;
 #pragma unroll
             for (int k = 0; k < 2; ++k)
@@ -120,8 +138,7 @@ __global__ void k_generate(GenParams P, int r0, double* __restrict__ out)
                 for (int j = 0; j < 2; ++j)
 #pragma unroll
                     for (int i = 0; i < 2; ++i) {
-                        const double f = P.kind == KIND_GRAVITY ? corner_gz(xs[i], ys[j], zs[k])
-                                                                : corner_tmi(xs[i], ys[j], zs[k], P.w);
+                        const double f = F[k * per + j * P.cx + i];
                         // (-1)^(i+j+k) with 1-based indices: + when the
                         // 0-based index sum is odd
                         s += ((i + j + k) & 1) ? f : -f;
@@ -618,6 +635,14 @@ k_cols_spec(const double2* __restrict__ in, int ncols, void* __restrict__ spec, 
 hipError_t launch_twiddles(double2* t64, float2* t32, int n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_twiddles, dim3((n + 255) / 256), dim3(256), 0, s, t64, t32, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_corners(const GenParams& P, int nl, double* corners, hipStream_t s)
+{
+    const int64_t per = (int64_t)P.cx * P.cy;
+    dim3 grid((unsigned)((per + 255) / 256), (unsigned)(nl + 1));
+    hipLaunchKernelGGL(k_corners, grid, dim3(256), 0, s, P, corners);
     return hipGetLastError();
 }
 
