@@ -103,11 +103,15 @@ def pair_bytes(pr, Nx, Ny, esz, form):
     return 2 * spectra_bytes(pr, Nx, Ny, esz, form) + 2 * nx * ny * nz * esz + 2 * sx * sy * esz
 
 
+# the sources that define the product kernels (their traffic does not depend
+# on the host code)
+KERNEL_SOURCES = ["bttb_kernels.hip", "bttb_cols.hip", "fft_core.h", "kern_common.h", "bttb_internal.h"]
+
+
 def counter_traffic(kernel):
     """Scaled HBM bytes (FETCH_SIZE + WRITE_SIZE, rocprofv3 PMC runs) of one
     launch of `kernel`, from the committed profile summary -- only if the
     kernel sources are unchanged since the counters were taken, else None."""
-    import glob
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "hbm_counters_gravity_1024_fp32.md")
@@ -119,8 +123,8 @@ def counter_traffic(kernel):
     info = json.loads(m.group(1))
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1912_06976_amd", "csrc")
-    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
-        h.update(open(f, "rb").read())
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     if h.hexdigest() != info.get("source_sha256"):
         return None
     k = info.get("kernels", {}).get(kernel)

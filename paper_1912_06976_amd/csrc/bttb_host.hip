@@ -328,23 +328,33 @@ struct Item {
     char* ws;         // this item's workspace (layout ws_layout(P, nrhs))
 };
 
-// Launch `jobs` (all of one transform length) in tables of at most MAX_JOBS.
+// Launch `jobs` (all of one transform length) in tables of at most MAX_JOBS
+// jobs and at most 2^31 - 1 work units (blocks, row groups or layer units).
 template <typename JobT, typename TableT, typename Launch>
-bttb_status launch_tables(const std::vector<JobT>& jobs, const std::vector<int>& work, Launch&& launch,
+bttb_status launch_tables(const std::vector<JobT>& jobs, const std::vector<int64_t>& work, Launch&& launch,
                           const char* what)
 {
-    for (size_t a = 0; a < jobs.size(); a += MAX_JOBS) {
+    constexpr int64_t kMax = 0x7fffffff;
+    size_t a = 0;
+    while (a < jobs.size()) {
         TableT tab{};
-        int total = 0;
-        for (size_t k = a; k < jobs.size() && k < a + MAX_JOBS; ++k) {
+        int64_t total = 0;
+        size_t k = a;
+        for (; k < jobs.size() && tab.njobs < MAX_JOBS; ++k) {
+            if (work[k] > kMax)
+                return fail(BTTB_ERR_UNSUPPORTED,
+                            std::string(what) + ": one problem needs more than 2^31 - 1 work units in one launch; "
+                                                "use fewer right-hand sides per call");
+            if (total + work[k] > kMax) break;
             tab.j[tab.njobs] = jobs[k];
-            tab.j[tab.njobs].begin = total;
+            tab.j[tab.njobs].begin = (int)total;
             total += work[k];
             ++tab.njobs;
         }
-        tab.total = total;
+        tab.total = (int)total;
         bttb_status st = hip_check(launch(tab), what);
         if (st != BTTB_OK) return st;
+        a = k;
     }
     return BTTB_OK;
 }
@@ -355,9 +365,9 @@ template <typename T>
 struct RowStage {
     std::vector<int> keys;
     std::vector<std::vector<RowJob>> jobs;
-    std::vector<std::vector<int>> work;
+    std::vector<std::vector<int64_t>> work;
     std::vector<const cT<T>*> tw;
-    void add(int N, int tile, const cT<T>* twp, const RowJob& j, int nbatch)
+    void add(int N, int tile, const cT<T>* twp, const RowJob& j, int64_t nbatch)
     {
         const int key = N * 16 + tile;
         size_t g = 0;
@@ -367,7 +377,7 @@ struct RowStage {
         const int rt = row_group_rows<T>(N, tile);
         jj.bpb = (j.nrows + rt - 1) / rt;
         jobs[g].push_back(jj);
-        work[g].push_back(jj.bpb * nbatch);
+        work[g].push_back((int64_t)jj.bpb * nbatch);
     }
 };
 
@@ -381,7 +391,7 @@ template <typename T>
 struct ColStage {
     std::vector<ColKey> keys;
     std::vector<std::vector<ColJob>> jobs;
-    std::vector<std::vector<int>> work;
+    std::vector<std::vector<int64_t>> work;
     std::vector<const cT<T>*> tw;
     // units: work items per (right-hand side, column block): 1 for the
     // forward kernel (one block each), the layers for the persistent
@@ -395,7 +405,7 @@ struct ColStage {
         const int cb = col_block_lines<T>(key.N, key.tile);
         jj.nbx = (j.ncols + cb - 1) / cb;
         jobs[g].push_back(jj);
-        work[g].push_back(jj.nbx * j.nrhs * units);
+        work[g].push_back((int64_t)jj.nbx * j.nrhs * units);
     }
 };
 
@@ -485,7 +495,7 @@ bttb_status run_forward(const std::vector<Item>& items, hipStream_t s, hipEvent_
         const int64_t pny = panel_rows(P->ny), psy = panel_rows(P->sy);
         r1.add(P->Nx, P->row_tile, tw_x<T>(P, it.spec),
                RowJob{it.in, X, (int64_t)P->nx * P->ny, P->nx, P->ncols * pny, 0, P->nx, P->ny, 0, 0},
-               it.nrhs * P->nz);
+               (int64_t)it.nrhs * P->nz);
         c2.add(ColKey{P->Ny, P->acc, P->col_tile, P->form}, tw_y<T>(P, it.spec),
                col_job(P, X, it.spec, Y, pny, psy, P->ny, P->sy, 0, P->nz, it.nrhs));
         r3.add(P->Nx, P->row_tile, tw_x<T>(P, it.spec),
@@ -541,7 +551,7 @@ bttb_status run_transpose(const std::vector<Item>& items, hipStream_t s, hipEven
             if (nl == P->nz) {
                 r3.add(P->Nx, P->row_tile, tw_x<T>(P, it.spec),
                        RowJob{Z, out, P->ncols * pny, 0, (int64_t)P->nx * P->ny, P->nx, P->nx, P->ny, 0, 0},
-                       it.nrhs * P->nz);
+                       (int64_t)it.nrhs * P->nz);
             } else {
                 for (int q = 0; q < it.nrhs; ++q)
                     r3.add(P->Nx, P->row_tile, tw_x<T>(P, it.spec),
