@@ -471,9 +471,8 @@ hipError_t launch_cols_fwd(int N, int tile, int form, const ColJobs& jobs, const
 template <typename T, int NN, int CM, int SF>
 static void launch_tr_n(const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
 {
-    static int resident = 0;
-    if (!resident)
-        resident = resident_blocks((const void*)k_cols_tr_mac<T, NN, 1, CM, SF>, ColCfg<NN, CM>::THREADS);
+    // thread-safe one-time initialisation (function-local static)
+    static const int resident = resident_blocks((const void*)k_cols_tr_mac<T, NN, 1, CM, SF>, ColCfg<NN, CM>::THREADS);
     hipLaunchKernelGGL((k_cols_tr_mac<T, NN, 1, CM, SF>), dim3(std::min(jobs.total, resident)),
                        dim3(ColCfg<NN, CM>::THREADS), 0, s, jobs, tw);
 }

@@ -686,8 +686,8 @@ template <typename TI, typename T, int NN, int P0>
 static hipError_t launch_r2c_n(const RowJobs& jobs, const cT<T>* tw, hipStream_t s)
 {
     using C = RowCfg<T, NN, P0>;
-    static int resident = 0;
-    if (!resident) resident = resident_blocks((const void*)k_rows_r2c<TI, T, NN, P0>, C::THREADS);
+    // thread-safe one-time initialisation (function-local static)
+    static const int resident = resident_blocks((const void*)k_rows_r2c<TI, T, NN, P0>, C::THREADS);
     hipLaunchKernelGGL((k_rows_r2c<TI, T, NN, P0>), dim3(std::min(jobs.total, resident)), dim3(C::THREADS), 0, s,
                        jobs, tw);
     return hipGetLastError();
@@ -697,8 +697,8 @@ template <typename T, int NN, int P0>
 static hipError_t launch_c2r_n(const RowJobs& jobs, const cT<T>* tw, hipStream_t s)
 {
     using C = RowCfg<T, NN, P0>;
-    static int resident = 0;
-    if (!resident) resident = resident_blocks((const void*)k_rows_c2r<T, NN, P0>, C::THREADS);
+    // thread-safe one-time initialisation (function-local static)
+    static const int resident = resident_blocks((const void*)k_rows_c2r<T, NN, P0>, C::THREADS);
     hipLaunchKernelGGL((k_rows_c2r<T, NN, P0>), dim3(std::min(jobs.total, resident)), dim3(C::THREADS), 0, s,
                        jobs, tw);
     return hipGetLastError();
@@ -708,8 +708,8 @@ template <typename TI, typename T, int NN>
 static hipError_t launch_r2c_t(const RowJobs& jobs, const cT<T>* tw, hipStream_t s)
 {
     using C = TileCfg<NN>;
-    static int resident = 0;
-    if (!resident) resident = resident_blocks((const void*)k_rows_r2c_t<TI, T, NN>, C::THREADS);
+    // thread-safe one-time initialisation (function-local static)
+    static const int resident = resident_blocks((const void*)k_rows_r2c_t<TI, T, NN>, C::THREADS);
     const int nb = (jobs.total + C::LPB - 1) / C::LPB;
     hipLaunchKernelGGL((k_rows_r2c_t<TI, T, NN>), dim3(std::min(nb, resident)), dim3(C::THREADS), 0, s, jobs, tw);
     return hipGetLastError();
@@ -719,8 +719,8 @@ template <typename T, int NN>
 static hipError_t launch_c2r_t(const RowJobs& jobs, const cT<T>* tw, hipStream_t s)
 {
     using C = TileCfg<NN>;
-    static int resident = 0;
-    if (!resident) resident = resident_blocks((const void*)k_rows_c2r_t<T, NN>, C::THREADS);
+    // thread-safe one-time initialisation (function-local static)
+    static const int resident = resident_blocks((const void*)k_rows_c2r_t<T, NN>, C::THREADS);
     const int nb = (jobs.total + C::LPB - 1) / C::LPB;
     hipLaunchKernelGGL((k_rows_c2r_t<T, NN>), dim3(std::min(nb, resident)), dim3(C::THREADS), 0, s, jobs, tw);
     return hipGetLastError();

@@ -317,3 +317,41 @@ def test_deterministic(torch_cuda):
     a = _products(torch_cuda, plan, m, v)
     b = _products(torch_cuda, plan, m, v)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_concurrent_calls_on_one_plan(torch_cuda):
+    # one plan, four host threads, each with its own stream and workspace:
+    # every result equals the sequential one bitwise
+    import threading
+    torch = torch_cuda
+    from paper_1912_06976_amd import Plan, bttb_forward, bttb_transpose
+    pr = W.magnetic_48x56()
+    plan = _plan(pr, "fp32")
+    m = torch.tensor(W.normal_model(pr, 91), dtype=torch.float32, device="cuda")
+    v = torch.tensor(W.normal_data(pr, 92), dtype=torch.float32, device="cuda")
+    ref_d, ref_t = plan.forward(m), plan.transpose(v)
+    torch.cuda.synchronize()
+    nws = plan.workspace_bytes(1)
+    errors, outs = [], {}
+
+    def work(k):
+        try:
+            s = torch.cuda.Stream()
+            ws = torch.empty(nws, dtype=torch.uint8, device="cuda")
+            d = torch.empty_like(ref_d)
+            t = torch.empty_like(ref_t)
+            for _ in range(5):
+                bttb_forward(plan.handle, plan.spectra, m, d, 1, ws, s)
+                bttb_transpose(plan.handle, plan.spectra, v, t, 1, ws, s)
+            s.synchronize()
+            outs[k] = (d, t)
+        except Exception as e:  # pragma: no cover - reported below
+            errors.append(e)
+    th = [threading.Thread(target=work, args=(k,)) for k in range(4)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    assert not errors, errors
+    for k in range(4):
+        assert torch.equal(outs[k][0], ref_d) and torch.equal(outs[k][1], ref_t)
