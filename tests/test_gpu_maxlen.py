@@ -1,0 +1,90 @@
+"""The longest supported transform (4096) along x and along y, with the data
+occupying more than half of it (no pruned first stage) and, with explicit
+lengths, less than half (pruned), against the oracle's dense matrix."""
+import numpy as np
+import pytest
+
+import workloads as W
+from _common import oracle_problem, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 2e-5}
+
+SHAPES = {
+    # Nx = 4096 (s + n - 1 = 2206), Ny = 8
+    "gravity_x4096": W.problem(W.GRAVITY, 1100, 2, 2, 3, 4, 1, 0, dx=25.0, dy=25.0, dz=20.0),
+    # Ny = 4096 (s + n - 1 = 2064), Nx = 8
+    "magnetic_y4096": W.problem(W.MAGNETIC, 3, 1030, 2, 1, 0, 2, 3, dx=50.0, dy=50.0, dz=25.0,
+                                incl=55.0, decl=-25.0, field_nT=47000.0),
+    # 4096 x 4096 requested for a small volume: pruned first stages both ways
+    "gravity_both4096": W.problem(W.GRAVITY, 12, 9, 3, 2, 1, 0, 3, dx=50.0, dy=50.0, dz=25.0,
+                                  nx_fft=4096, ny_fft=4096),
+}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+_DENSE = {}
+
+
+def _dense(name):
+    import oracle
+    if name not in _DENSE:
+        P = oracle_problem(SHAPES[name])
+        G, A = oracle.dense_G_quad(P, with_abs=True)
+        tq, _ = oracle.offset_table_quad(P)
+        _DENSE.clear()
+        _DENSE[name] = (G, A, tq)
+    return _DENSE[name]
+
+
+def _products(torch, plan, m, v):
+    d = plan.forward(torch.tensor(m, dtype=plan.dtype, device="cuda"))
+    t = plan.transpose(torch.tensor(v, dtype=plan.dtype, device="cuda"))
+    torch.cuda.synchronize()
+    return d.double().cpu().numpy().ravel(), t.double().cpu().numpy().ravel()
+
+
+@pytest.mark.parametrize("name", list(SHAPES))
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("form", ["auto", "complex"])
+def test_longest_transform(torch_cuda, name, prec, form):
+    from paper_1912_06976_amd import Plan
+    torch = torch_cuda
+    pr = dict(SHAPES[name], spectrum_form=form)
+    if form == "complex" and pr["kind"] != W.GRAVITY:
+        pytest.skip("the complex form is the only one for this kernel (covered by 'auto')")
+    print("longest transform", name, prec, form, flush=True)
+    G, A, tq = _dense(name)
+    m = W.normal_model(pr, 4100).ravel()
+    v = W.normal_data(pr, 4200).ravel()
+    tol = TOL[prec]
+
+    plan = Plan(pr, prec).generate()
+    assert 4096 in (plan.nx_fft, plan.ny_fft)
+    d, t = _products(torch, plan, m.reshape(W.normal_model(pr, 0).shape), v.reshape(pr["sy"], pr["sx"]))
+    # FP64 entries of distant prisms carry the rounding of their cancelling
+    # corner sums (bound c eps sum|corner terms|, A); the product is held to
+    # the larger of the bar and that bound propagated
+    eps = np.finfo(float).eps
+    for got, ref, bnd in ((d, G @ m, 32 * eps * (A @ np.abs(m))), (t, G.T @ v, 32 * eps * (A.T @ np.abs(v)))):
+        err, nref = np.linalg.norm(got - ref), np.linalg.norm(ref)
+        assert err <= max(tol * nref, np.linalg.norm(bnd) + 1e-13 * nref), err / nref
+    form_used = plan.spectrum_form
+    del plan
+
+    # the exact entries as a table: the stated bar, no entry rounding left
+    plan_t = Plan(dict(pr, kind=W.TABLE, spectrum_form=form_used), prec)
+    plan_t.generate(table=torch.tensor(np.ascontiguousarray(tq), dtype=torch.float64, device="cuda"))
+    d, t = _products(torch, plan_t, m.reshape(W.normal_model(pr, 0).shape), v.reshape(pr["sy"], pr["sx"]))
+    assert rel_l2(d, G @ m) <= tol
+    assert rel_l2(t, G.T @ v) <= tol
+    del plan_t
+    torch.cuda.empty_cache()
