@@ -7,10 +7,13 @@ gravity volume of 1000 x 1000 stations, 12 padding cells per side
 generation is timed separately), inputs resident in HBM.  The metric is model
 cells per second: nx * ny * nz / (time of one step).
 
-Prints one JSON line.  Besides the headline FP32 number it reports the FP64
-path, the kernel-generation time, per-kernel times from HIP events recorded on
-the launch stream, the roofline of the dominant kernel, and the CPU oracle's
-rate on a bounded sample of the same workload.
+Prints one JSON line.  Besides the headline FP32 number (the mean over K
+steps in one timed region) it reports the mean, median and extremes of single
+steps, the FP64 path, the kernel-generation time, per-kernel times from HIP
+events recorded on the launch stream, the roofline of the dominant kernel
+(against the 8 TB/s HBM peak and against the rate of a plain device copy
+measured in the same run), and the CPU oracle's rate on a bounded sample of
+the same workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -157,6 +160,18 @@ def run_gpu(torch, B, pr, prec, m_host, r_host, steps, warmup, want_kernels=True
     e1.record(s)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    # the same steps once more, each between its own events (mean, median
+    # and extremes of single steps; the figure above is the aggregate)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(s)
+    for i in range(steps):
+        plan.forward(m, out=d)
+        plan.transpose(r, out=mt)
+        ev[i + 1].record(s)
+    torch.cuda.synchronize()
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    step_stats = {"n": steps, "mean": round(float(per.mean()), 4), "median": round(float(np.median(per)), 4),
+                  "min": round(float(per.min()), 4), "max": round(float(per.max()), 4)}
     kern = None
     if want_kernels:
         acc = np.zeros(6)
@@ -165,8 +180,28 @@ def run_gpu(torch, B, pr, prec, m_host, r_host, steps, warmup, want_kernels=True
             t = B.bttb_transpose_profiled(plan.handle, plan.spectra, r, mt, 1, ws)
             acc += np.array(f + t)
         kern = dict(zip(KERNELS_FWD + KERNELS_TR, (acc / steps).tolist()))
-    out = dict(plan=plan, ms=ms, gen_ms=gen_ms, kernels=kern, d=d, mt=mt, m=m, r=r)
+    out = dict(plan=plan, ms=ms, step_stats=step_stats, gen_ms=gen_ms, kernels=kern, d=d, mt=mt, m=m, r=r)
     return out
+
+
+def copy_rate(torch, nbytes=1 << 30, reps=10):
+    """Read + write rate of a plain device copy (torch copy_) of nbytes: the
+    practical streaming rate the HBM-bound kernels are compared with."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(gbs, 1)
 
 
 def run_batch(torch, B, steps):
@@ -240,8 +275,8 @@ def run_autograd(torch, B, steps):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-stations", type=int, default=40)
@@ -317,8 +352,10 @@ def main():
     # closer to
     kf = kernel_flops(pr, Nx, Ny, form)
     t_dom = kern[dom] * 1e-3
+    copy_gbs = copy_rate(torch)
     hbm = {"achieved": round(kb[dom] / t_dom / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     hbm["frac"] = round(hbm["achieved"] / HBM_PEAK_GBS, 4)
+    hbm["frac_vs_copy"] = round(hbm["achieved"] / copy_gbs, 4)
     alu = {"achieved": round(kf[dom] / t_dom / 1e12, 2), "peak": round(VALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s"}
     alu["frac"] = round(alu["achieved"] / VALU_PEAK_TFLOPS, 4)
     use_alu = alu["frac"] > hbm["frac"]
@@ -344,6 +381,8 @@ def main():
         "kernel_ms": {k: round(v, 4) for k, v in kern.items()},
         "kernel_rates": {k: {"GB/s": round(kb[k] / (kern[k] * 1e-3) / 1e9, 1),
                              "TFLOP/s": round(kf[k] / (kern[k] * 1e-3) / 1e12, 2)} for k in kern},
+        "step_ms_stats": g32["step_stats"],
+        "hbm_copy_GBps": copy_gbs,
         "generate_ms": round(g32["gen_ms"], 2),
     }
 
