@@ -169,10 +169,14 @@ k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
     cT<T>* __restrict__ Y = (cT<T>*)J.b;
     const int64_t ldx = J.lda, ldy = J.ldb;
     const int ny = J.na, sy = J.nb, nz = J.nl, ncols = J.ncols, nrhs = J.nrhs;
-    const int lb = bid - J.begin, cb = lb % J.nbx;
+    // the right-hand-side blocks of one column block are consecutive blocks,
+    // which run at the same time on one XCD and share that column's spectra
+    // through its L2
+    const int nqb = (J.nrhs + NR - 1) / NR;
+    const int lb = bid - J.begin, cb = lb / nqb;
     const int cl = threadIdx.x / TPL, t = threadIdx.x % TPL;
     const int col = cb * C::CPW + cl;
-    const int q0 = (lb / J.nbx) * NR;
+    const int q0 = (lb % nqb) * NR;
     const bool ok = col < ncols;
     const bool packed_blk = cb == 0;              // block holding column 0
     const bool packed = packed_blk && cl == 0;
@@ -293,8 +297,10 @@ k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
 // R + q * ncols * lda, y < na = sy; b = Z, block (q, r - r0) at
 // Z + (q * nl + r - r0) * ncols * ldb, y < nb = ny.
 // The kernel is persistent and balanced: the work of all jobs is the list of
-// units (job, right-hand side q, column block cb, layer l), layer fastest,
-// and block w processes the contiguous range [w U / G, (w + 1) U / G).  A
+// units (job, column block cb, right-hand side q, layer l), layer fastest,
+// and block w processes the contiguous range [w U / G, (w + 1) U / G).  The
+// right-hand sides of one column block thus fall to neighbouring blocks,
+// which run at the same time on one XCD and share its spectra through L2.  A
 // block recomputes R^ = FFT_y(R) whenever its range enters a new column
 // block (at most a few times), so every block gets the same number of layers
 // whatever the number of resident blocks.
@@ -312,11 +318,12 @@ k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
     LineTwiddles<T, N> twl;
     twl.load(tw, t);
     const int64_t U = jobs.total, G = gridDim.x;
-    // XCD-ordered: blocks with neighbouring unit ranges (neighbouring column
-    // blocks, whose panel segments share 128-byte lines) run on one XCD
+    // XCD-ordered: blocks with neighbouring unit ranges (the right-hand
+    // sides of one column block, then neighbouring column blocks, whose
+    // panel segments share 128-byte lines) run on one XCD
     const int w = xcd_order(blockIdx.x, (int)G);
     const int u0 = (int)((int64_t)w * U / G), u1 = (int)((int64_t)(w + 1) * U / G);
-    // unit u -> (job k, key = q * nbx + cb, layer l)
+    // unit u -> (job k, key = cb * nrhs + q, layer l)
     auto decode = [&](int u, int& k, int& key, int& l) {
         k = find_job(jobs, u);
         const int lu = u - jobs.j[k].begin;
@@ -328,7 +335,7 @@ k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
         int k, key, l;
         decode(u, k, key, l);
         const ColJob& J = jobs.j[k];
-        const int cb = key % J.nbx;
+        const int cb = key / J.nrhs;
         const int col = cb * C::CPW + cl;
         const int ccol = col < J.ncols ? col : 0;
         if constexpr (SF == FORM_COMPLEX) {
@@ -348,7 +355,7 @@ k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
         int k, key, l;
         decode(u, k, key, l);
         const ColJob& J = jobs.j[k];
-        const int cb = key % J.nbx, q = key / J.nbx;
+        const int cb = key / J.nrhs, q = key % J.nrhs;
         const int col = cb * C::CPW + cl;
         const bool ok = col < J.ncols;
         const bool packed_blk = cb == 0;
