@@ -169,15 +169,30 @@ __device__ __forceinline__ cT<T> tw_get(const TableTwiddles<T, N>& tw, int, int 
     return tw.p[TableTwiddles<T, N>::off(s) + (i - 1) * L + j];
 }
 
+// Ordering of one wavefront's LDS writes and reads without a block barrier:
+// the LDS executes a wavefront's operations in issue order, so a scheduling
+// barrier between wavefront-scope fences suffices for lanes of one wavefront
+// to read what other lanes of it wrote.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename T, int DIR> __device__ __forceinline__ cT<T> twmul(cT<T> a, cT<T> w) {
     return DIR < 0 ? cmul<T>(a, w) : cmulc<T>(a, w);
 }
 
 // In-place transform of one line.  v[m] holds position t + m * TPL on entry
 // and on exit.  lds points at this line's padded buffer of
-// lds_line_elems(N) elements.  SYNC must be a block-wide barrier (all lines
-// of the block run the same stages).  ZERO_HI: positions >= N / 2 are known
-// to be zero on entry (pruned first stage).
+// lds_line_elems(N) elements.  Every thread of the block calls it (all lines
+// of the block run the same stages; a line is TPL consecutive threads).  The
+// first exchange begins with a block barrier, so the buffer may overlap LDS
+// that other wavefronts used before the call; the remaining exchanges of a
+// line that lies within one wavefront (TPL <= 64) synchronise only that
+// wavefront.  ZERO_HI: positions >= N / 2 are known to be zero on entry
+// (pruned first stage).
 template <typename T, int N, int DIR, bool ZERO_HI = false, typename TW = LineTwiddles<T, N>>
 __device__ __forceinline__ void fft_line(cT<T> (&v)[8], cT<T>* __restrict__ lds, const TW& tw, int t)
 {
@@ -214,12 +229,15 @@ __device__ __forceinline__ void fft_line(cT<T> (&v)[8], cT<T>* __restrict__ lds,
         }
         const bool last = (s == S::S8 - 1) && (S::RL == 1);
         if (!last) {
+            constexpr bool WAVE_LOCAL = TPL <= 64;
             const int j = t % L;
             const int base = (t / L) * L * 8 + j;
-            __syncthreads();
+            if (!WAVE_LOCAL || s == 0) __syncthreads();
+            else wave_lds_sync();
 #pragma unroll
             for (int i = 0; i < 8; ++i) lds[lpad(base + i * L)] = v[i];
-            __syncthreads();
+            if (WAVE_LOCAL) wave_lds_sync();
+            else __syncthreads();
 #pragma unroll
             for (int m = 0; m < 8; ++m) v[m] = lds[lpad(t + m * TPL)];
         }
