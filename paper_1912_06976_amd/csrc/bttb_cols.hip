@@ -34,6 +34,7 @@ template <typename T> struct Acc<T, ACC_PLAIN> {
     __device__ __forceinline__ void zero() { s = mk<T>(0, 0); }
     __device__ __forceinline__ void add(cT<T> p) { s.x += p.x; s.y += p.y; }
     __device__ __forceinline__ cT<T> get() const { return s; }
+    __device__ __forceinline__ double2 wide() const { return make_double2(s.x, s.y); }
 };
 // compensated (TwoSum) accumulation in the working precision
 template <typename T> struct Acc<T, ACC_TWOSUM> {
@@ -48,6 +49,9 @@ template <typename T> struct Acc<T, ACC_TWOSUM> {
     }
     __device__ __forceinline__ void add(cT<T> p) { two_sum(s.x, c.x, p.x); two_sum(s.y, c.y, p.y); }
     __device__ __forceinline__ cT<T> get() const { return mk<T>(s.x + c.x, s.y + c.y); }
+    __device__ __forceinline__ double2 wide() const {
+        return make_double2((double)s.x + (double)c.x, (double)s.y + (double)c.y);
+    }
 };
 // FP64 accumulation of FP32 products
 template <typename T> struct Acc<T, ACC_WIDE> {
@@ -55,6 +59,7 @@ template <typename T> struct Acc<T, ACC_WIDE> {
     __device__ __forceinline__ void zero() { sx = 0.0; sy = 0.0; }
     __device__ __forceinline__ void add(cT<T> p) { sx += (double)p.x; sy += (double)p.y; }
     __device__ __forceinline__ cT<T> get() const { return mk<T>((T)sx, (T)sy); }
+    __device__ __forceinline__ double2 wide() const { return make_double2(sx, sy); }
 };
 
 // Column 0 of the packed format holds z = A + i B with A, B the transforms
@@ -147,11 +152,41 @@ __device__ __forceinline__ void load_real_even(cT<T> (&tn)[8], const ColJob& J, 
     }
 }
 
+// End of the forward column pass for one line: the depth sum w of column
+// `col` (positions t + m TPL) times the phase of the real even form, the
+// inverse y transform, and the store of rows y < nb into block q of Y
+// (`store` false: transform only, every thread of the block takes part).
+template <typename T, int N, int SF>
+__device__ __forceinline__ void fwd_finish(cT<T> (&w)[8], const ColJob& J, int col, bool packed, bool store, int q,
+                                           cT<T>* xl, const LineTwiddles<T, N>& twl, int t)
+{
+    constexpr int TPL = N / 8;
+    if constexpr (SF == FORM_REAL_EVEN) {
+        // T^ = P R: the phase of this column (kx = 0 for the packed one)
+        const int ax = packed ? 0 : (int)(((int64_t)J.px * col) & (2 * J.ncols - 1));
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+            w[m] = cmul<T>(w[m], phase<T>(ax, 2 * J.ncols, (int)(((int64_t)J.py * (t + m * TPL)) & (N - 1)), N));
+    }
+    fft_line<T, N, +1, false>(w, xl, twl, t);
+    if (store) {
+        cT<T>* ys = (cT<T>*)J.b + (int64_t)q * J.ncols * J.ldb;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int y = t + m * TPL;
+            if (y < J.nb) ys[pidx(col, y, J.ncols)] = w[m];
+        }
+    }
+}
+
 // Forward column pass over every job of the table (one block per CPW
-// columns of one right-hand-side block of one job).  Job: a = X, the packed
-// row-pass output in panels, block (q, r) at X + (q * nz + r) * ncols * lda,
-// y < na = ny, nl = nz layers; b = Y, block q at Y + q * ncols * ldb,
-// y < nb = sy.
+// columns of one right-hand-side block and one layer range of one job).
+// Job: a = X, the packed row-pass output in panels, block (q, r) at
+// X + (q * nz + r) * ncols * lda, y < na = ny, nl = nz layers; b = Y, block
+// q at Y + q * ncols * ldb, y < nb = sy.  With ns = 1 a block sums all
+// layers and finishes the column; with ns > 1 the layers are split into ns
+// ranges and a block writes its range's sum, in FP64, to the partial sums p
+// (k_cols_fwd_fin adds them in range order and finishes).
 template <typename T, int N, int NR, int ACC, int CM, int SF>
 __global__ void __launch_bounds__((ColCfg<N, CM>::THREADS), (col_waves<T>()))
 k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
@@ -166,17 +201,17 @@ k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
     const ColJob& J = jobs.j[find_job(jobs, bid)];
     const cT<T>* __restrict__ X = (const cT<T>*)J.a;
     const cT<T>* __restrict__ spec = (const cT<T>*)J.spec;
-    cT<T>* __restrict__ Y = (cT<T>*)J.b;
-    const int64_t ldx = J.lda, ldy = J.ldb;
-    const int ny = J.na, sy = J.nb, nz = J.nl, ncols = J.ncols, nrhs = J.nrhs;
+    const int64_t ldx = J.lda;
+    const int ny = J.na, nz = J.nl, ncols = J.ncols, nrhs = J.nrhs;
     // the right-hand-side blocks of one column block are consecutive blocks,
     // which run at the same time on one XCD and share that column's spectra
     // through its L2
-    const int nqb = (J.nrhs + NR - 1) / NR;
-    const int lb = bid - J.begin, cb = lb / nqb;
+    const int nqb = (J.nrhs + NR - 1) / NR, ns = J.ns;
+    const int lb = bid - J.begin, rest = lb / nqb, split = rest % ns, cb = rest / ns;
     const int cl = threadIdx.x / TPL, t = threadIdx.x % TPL;
     const int col = cb * C::CPW + cl;
     const int q0 = (lb % nqb) * NR;
+    const int rb = (int)((int64_t)split * nz / ns), re = (int)((int64_t)(split + 1) * nz / ns);
     const bool ok = col < ncols;
     const bool packed_blk = cb == 0;              // block holding column 0
     const bool packed = packed_blk && cl == 0;
@@ -214,8 +249,8 @@ k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
         }
     };
     constexpr bool PIPE = true;
-    if (PIPE) load_layer(0);
-    for (int r = 0; r < nz; ++r) {
+    if (PIPE) load_layer(rb);
+    for (int r = rb; r < re; ++r) {
         if (!PIPE) load_layer(r);
         cT<T> tv[8], v[NR][8];
 #pragma unroll
@@ -224,7 +259,7 @@ k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
         for (int q = 0; q < NR; ++q)
 #pragma unroll
             for (int m = 0; m < 8; ++m) v[q][m] = xn[q][m];
-        if (PIPE && r + 1 < nz) load_layer(r + 1);
+        if (PIPE && r + 1 < re) load_layer(r + 1);
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
             if (zhi) fft_line<T, N, -1, true>(v[q], xl, twl, t);
@@ -267,29 +302,67 @@ k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
             }
         }
     }
+    if (ns > 1) {
+        // this layer range's sum, for k_cols_fwd_fin (ns is uniform in the
+        // block: no thread is left at a barrier)
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            const int qq = q0 + q;
+            if (ok && qq < nrhs) {
+                double2* pp = (double2*)J.p + (((int64_t)qq * ns + split) * ncols + col) * N;
+#pragma unroll
+                for (int m = 0; m < 8; ++m) pp[t + m * TPL] = acc[q][m].wide();
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
         const int qq = q0 + q;
         cT<T> w[8];
 #pragma unroll
         for (int m = 0; m < 8; ++m) w[m] = acc[q][m].get();
-        if constexpr (SF == FORM_REAL_EVEN) {
-            // T^ = P R: the phase of this column (kx = 0 for the packed one)
-            const int ax = packed ? 0 : (int)(((int64_t)J.px * ccol) & (2 * ncols - 1));
+        fwd_finish<T, N, SF>(w, J, ccol, packed, ok && qq < nrhs, qq, xl, twl, t);
+    }
+}
+
+// Finishing kernel of the forward column pass for jobs with ns > 1: one
+// block per CPW columns of one right-hand side (block order as in
+// k_cols_fwd_mac), which adds the ns partial depth sums in range order in
+// FP64 and finishes the columns (phase, inverse y transform, store).
+template <typename T, int N, int CM, int SF>
+__global__ void __launch_bounds__((ColCfg<N, CM>::THREADS)) k_cols_fwd_fin(ColJobs jobs, const cT<T>* __restrict__ tw)
+{
+    using C = ColCfg<N, CM>;
+    constexpr int TPL = C::TPL;
+    constexpr int LL = lds_line_elems(N);
+    __shared__ cT<T> lds[C::CPW * LL];
+    const int bid = xcd_order(blockIdx.x, gridDim.x);
+    const ColJob& J = jobs.j[find_job(jobs, bid)];
+    const int lb = bid - J.begin, q = lb % J.nrhs, cb = lb / J.nrhs;
+    const int cl = threadIdx.x / TPL, t = threadIdx.x % TPL;
+    const int col = cb * C::CPW + cl, ns = J.ns;
+    const bool ok = col < J.ncols;
+    LineTwiddles<T, N> twl;
+    twl.load(tw, t);
+    double sx[8], sy[8];
 #pragma unroll
-            for (int m = 0; m < 8; ++m)
-                w[m] = cmul<T>(w[m], phase<T>(ax, 2 * ncols, (int)(((int64_t)J.py * (t + m * TPL)) & (N - 1)), N));
-        }
-        fft_line<T, N, +1, false>(w, xl, twl, t);
-        if (ok && qq < nrhs) {
-            cT<T>* ys = Y + (int64_t)qq * ncols * ldy;
+    for (int m = 0; m < 8; ++m) sx[m] = sy[m] = 0.0;
+    if (ok) {
+        const double2* pp = (const double2*)J.p + ((int64_t)q * ns * J.ncols + col) * N;
+        for (int s = 0; s < ns; ++s, pp += (int64_t)J.ncols * N) {
 #pragma unroll
             for (int m = 0; m < 8; ++m) {
-                const int y = t + m * TPL;
-                if (y < sy) ys[pidx(col, y, ncols)] = w[m];
+                const double2 v = pp[t + m * TPL];
+                sx[m] += v.x;
+                sy[m] += v.y;
             }
         }
     }
+    cT<T> w[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) w[m] = mk<T>((T)sx[m], (T)sy[m]);
+    fwd_finish<T, N, SF>(w, J, ok ? col : 0, cb == 0 && cl == 0, ok, q, lds + cl * LL, twl, t);
 }
 
 // Transpose column pass over every job of the table, layers [r0, r0 + nl).
@@ -474,6 +547,32 @@ hipError_t launch_cols_fwd(int N, int tile, int form, const ColJobs& jobs, const
                                   : launch_fwd_form<T, ACC, FORM_COMPLEX>(N, tile, jobs, tw, s);
 }
 
+template <typename T, int SF>
+static hipError_t launch_fin_form(int N, int tile, const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
+{
+#define L_FIN(NN)                                                                          \
+    if constexpr (col_tile2_fits<T, NN>()) {                                               \
+        if (tile == 2) {                                                                   \
+            hipLaunchKernelGGL((k_cols_fwd_fin<T, NN, 2, SF>), dim3(jobs.total),           \
+                               dim3(ColCfg<NN, 2>::THREADS), 0, s, jobs, tw);              \
+            break;                                                                         \
+        }                                                                                  \
+    }                                                                                      \
+    hipLaunchKernelGGL((k_cols_fwd_fin<T, NN, 1, SF>), dim3(jobs.total), dim3(ColCfg<NN, 1>::THREADS), \
+                       0, s, jobs, tw);
+    BTTB_LEN_SWITCH(N, L_FIN)
+#undef L_FIN
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cols_fwd_fin(int N, int tile, int form, const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
+{
+    if (jobs.total <= 0) return hipSuccess;
+    return form == FORM_REAL_EVEN ? launch_fin_form<T, FORM_REAL_EVEN>(N, tile, jobs, tw, s)
+                                  : launch_fin_form<T, FORM_COMPLEX>(N, tile, jobs, tw, s);
+}
+
 // persistent: as many blocks as are resident at once (at most one per unit)
 template <typename T, int NN, int CM, int SF>
 static void launch_tr_n(const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
@@ -512,6 +611,8 @@ template hipError_t launch_cols_fwd<double, ACC_PLAIN>(int, int, int, const ColJ
 template hipError_t launch_cols_fwd<float, ACC_PLAIN>(int, int, int, const ColJobs&, const float2*, hipStream_t);
 template hipError_t launch_cols_fwd<float, ACC_TWOSUM>(int, int, int, const ColJobs&, const float2*, hipStream_t);
 template hipError_t launch_cols_fwd<float, ACC_WIDE>(int, int, int, const ColJobs&, const float2*, hipStream_t);
+template hipError_t launch_cols_fwd_fin<double>(int, int, int, const ColJobs&, const double2*, hipStream_t);
+template hipError_t launch_cols_fwd_fin<float>(int, int, int, const ColJobs&, const float2*, hipStream_t);
 template hipError_t launch_cols_tr<double>(int, int, int, const ColJobs&, const double2*, hipStream_t);
 template hipError_t launch_cols_tr<float>(int, int, int, const ColJobs&, const float2*, hipStream_t);
 

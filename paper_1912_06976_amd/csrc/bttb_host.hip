@@ -60,6 +60,7 @@ struct bttb_plan_s {
     int gen_batch;
     int tr_chunk;
     int row_tile, col_tile;      // kernel tile choices (see bttb_problem_desc)
+    int fwd_nbx;                 // column blocks of the forward MAC at column tile 1
     int form;                    // FORM_COMPLEX or FORM_REAL_EVEN
     int64_t ldr;                 // real even spectra: line stride (elements)
     int bx, by;                  // real even spectra: largest |offset| used in x and y
@@ -205,15 +206,38 @@ bttb_status validate_and_fill(const bttb_problem_desc* d, bttb_plan_s* P)
     P->tr_chunk = d->layer_chunk > 0 ? std::min(d->layer_chunk, P->nz) : P->nz;
     P->row_tile = d->row_tile ? d->row_tile : 4;
     P->col_tile = d->col_tile ? d->col_tile : 1;
+    // (counted at column tile 1, so that the depth split, and with it the
+    // rounding, does not depend on the tile choice)
+    const int cbl = P->fp64 ? col_block_lines<double>(Ny, 1) : col_block_lines<float>(Ny, 1);
+    P->fwd_nbx = (P->ncols + cbl - 1) / cbl;
     return BTTB_OK;
 }
 
 struct WsLayout {
     size_t gen_a, gen_b, gen_c, gen_total;
-    size_t fwd_x, fwd_y, fwd_total;
+    size_t fwd_x, fwd_y, fwd_p, fwd_total;
     size_t tr_r, tr_z, tr_total;
     size_t total;
 };
+
+// Layer ranges per column block of the forward MAC.  The kernel runs one
+// block per column block and right-hand side, each summing its layers in
+// turn; when a launch has few such blocks (`blocks`, over all its jobs) most
+// of the device would idle, so the layers are split into ranges (at least 4
+// layers each) until there are about two blocks per resident slot.  The
+// ranges' FP64 sums are added in range order by a finishing kernel.  The
+// split, and with it the rounding, is a function of the plan, the
+// right-hand-side count and the launch's block count: repeated calls give
+// the same results; a batch, whose launches hold more blocks, may split less
+// than single calls and then differs from them by rounding.
+int fwd_split(const bttb_plan_s* P, int64_t blocks)
+{
+    const int64_t target = P->fp64 ? 512 : 1024;
+    const int64_t want = (target + blocks - 1) / std::max<int64_t>(1, blocks);
+    return (int)std::max<int64_t>(1, std::min<int64_t>({want, P->nz / 4, 64}));
+}
+// the largest split of a plan's own launch with nrhs right-hand sides
+int fwd_split(const bttb_plan_s* P, int nrhs) { return fwd_split(P, (int64_t)P->fwd_nbx * nrhs); }
 
 WsLayout ws_layout(const bttb_plan_s* P, int nrhs)
 {
@@ -227,7 +251,9 @@ WsLayout ws_layout(const bttb_plan_s* P, int nrhs)
     const size_t pny = (size_t)panel_rows(P->ny), psy = (size_t)panel_rows(P->sy);
     L.fwd_x = 0;
     L.fwd_y = align_up((size_t)nrhs * P->nz * P->ncols * pny * csz);
-    L.fwd_total = align_up(L.fwd_y + (size_t)nrhs * P->ncols * psy * csz);
+    L.fwd_p = align_up(L.fwd_y + (size_t)nrhs * P->ncols * psy * csz);
+    const int ns = fwd_split(P, nrhs);
+    L.fwd_total = align_up(L.fwd_p + (ns > 1 ? (size_t)nrhs * ns * P->ncols * (size_t)P->Ny * 16 : 0));
     L.tr_r = 0;
     L.tr_z = align_up((size_t)nrhs * P->ncols * psy * csz);
     L.tr_total = align_up(L.tr_z + (size_t)nrhs * P->tr_chunk * P->ncols * pny * csz);
@@ -393,9 +419,9 @@ struct ColStage {
     std::vector<std::vector<ColJob>> jobs;
     std::vector<std::vector<int64_t>> work;
     std::vector<const cT<T>*> tw;
-    // units: work items per (right-hand side, column block): 1 for the
-    // forward kernel (one block each), the layers for the persistent
-    // transpose kernel
+    // units: work items per (right-hand side, column block): the layer
+    // ranges of the forward kernel (one block each), the layers of the
+    // persistent transpose kernel, 1 for the forward finishing kernel
     void add(const ColKey& key, const cT<T>* twp, const ColJob& j, int units = 1)
     {
         size_t g = 0;
@@ -455,6 +481,21 @@ bttb_status run_cols(const ColStage<T>& st, bool fwd, hipStream_t s)
     return BTTB_OK;
 }
 
+// the finishing launches of forward column jobs with depth splits
+template <typename T>
+bttb_status run_cols_fin(const ColStage<T>& st, hipStream_t s)
+{
+    for (size_t g = 0; g < st.keys.size(); ++g) {
+        const ColKey k = st.keys[g];
+        const cT<T>* tw = st.tw[g];
+        bttb_status r = launch_tables<ColJob, ColJobs>(st.jobs[g], st.work[g], [&](const ColJobs& t) {
+            return launch_cols_fwd_fin<T>(k.N, k.tile, k.form, t, tw, s);
+        }, "forward column sums");
+        if (r != BTTB_OK) return r;
+    }
+    return BTTB_OK;
+}
+
 // a column job of plan P (the form-specific fields filled in)
 ColJob col_job(const bttb_plan_s* P, const void* a, const char* spec, void* b, int64_t lda, int64_t ldb, int na,
                int nb, int r0, int nl, int nrhs)
@@ -474,6 +515,8 @@ ColJob col_job(const bttb_plan_s* P, const void* a, const char* spec, void* b, i
     j.px = P->d.pxl;
     j.py = P->d.pyl;
     j.lds = P->ldr;
+    j.p = nullptr;
+    j.ns = 1;
     return j;
 }
 
@@ -486,7 +529,18 @@ template <typename T>
 bttb_status run_forward(const std::vector<Item>& items, hipStream_t s, hipEvent_t* ev = nullptr)
 {
     RowStage<T> r1, r3;
-    ColStage<T> c2;
+    ColStage<T> c2, c2f;
+    // forward MAC blocks per column launch group (transform length, tile,
+    // form, accumulation), for the depth split
+    std::vector<std::pair<ColKey, int64_t>> group_blocks;
+    for (const Item& it : items) {
+        const bttb_plan_s* P = it.P;
+        const ColKey key{P->Ny, P->acc, P->col_tile, P->form};
+        size_t g = 0;
+        while (g < group_blocks.size() && !(group_blocks[g].first == key)) ++g;
+        if (g == group_blocks.size()) group_blocks.push_back({key, 0});
+        group_blocks[g].second += (int64_t)P->fwd_nbx * it.nrhs;
+    }
     for (const Item& it : items) {
         const bttb_plan_s* P = it.P;
         const WsLayout L = ws_layout(P, it.nrhs);
@@ -496,8 +550,13 @@ bttb_status run_forward(const std::vector<Item>& items, hipStream_t s, hipEvent_
         r1.add(P->Nx, P->row_tile, tw_x<T>(P, it.spec),
                RowJob{it.in, X, (int64_t)P->nx * P->ny, P->nx, P->ncols * pny, 0, P->nx, P->ny, 0, 0},
                (int64_t)it.nrhs * P->nz);
-        c2.add(ColKey{P->Ny, P->acc, P->col_tile, P->form}, tw_y<T>(P, it.spec),
-               col_job(P, X, it.spec, Y, pny, psy, P->ny, P->sy, 0, P->nz, it.nrhs));
+        const ColKey key{P->Ny, P->acc, P->col_tile, P->form};
+        ColJob cj = col_job(P, X, it.spec, Y, pny, psy, P->ny, P->sy, 0, P->nz, it.nrhs);
+        for (const auto& gb : group_blocks)
+            if (gb.first == key) cj.ns = fwd_split(P, gb.second);
+        cj.p = it.ws + L.fwd_p;
+        c2.add(key, tw_y<T>(P, it.spec), cj, cj.ns);
+        if (cj.ns > 1) c2f.add(ColKey{P->Ny, 0, P->col_tile, P->form}, tw_y<T>(P, it.spec), cj);
         r3.add(P->Nx, P->row_tile, tw_x<T>(P, it.spec),
                RowJob{Y, it.out, P->ncols * psy, 0, (int64_t)P->sx * P->sy, P->sx, P->sx, P->sy, 0, 0},
                it.nrhs);
@@ -507,6 +566,7 @@ bttb_status run_forward(const std::vector<Item>& items, hipStream_t s, hipEvent_
     if ((st = run_rows_r2c<T, T>(r1, s)) != BTTB_OK) return st;
     if ((st = record(ev, 1, s)) != BTTB_OK) return st;
     if ((st = run_cols<T>(c2, true, s)) != BTTB_OK) return st;
+    if ((st = run_cols_fin<T>(c2f, s)) != BTTB_OK) return st;
     if ((st = record(ev, 2, s)) != BTTB_OK) return st;
     if ((st = run_rows_c2r<T>(r3, s)) != BTTB_OK) return st;
     return record(ev, 3, s);
@@ -1002,7 +1062,13 @@ bttb_status bttb_batch_create(const bttb_plan_t* plans, int32_t nplans, int32_t 
             }
             B->plans.push_back(plans[k]);
             B->ws_off.push_back(B->ws_total);
-            B->ws_total = align_up(B->ws_total + ws_layout(plans[k], max_nrhs).total);
+            // an item may run with fewer right-hand sides, whose layout (the
+            // forward's depth split depends on the count) is not always smaller
+            // (beyond 1024 right-hand sides there is no split and the layout
+            // grows with the count)
+            size_t need = ws_layout(plans[k], max_nrhs).total;
+            for (int n = 1; n <= std::min(max_nrhs, 1024); ++n) need = std::max(need, ws_layout(plans[k], n).total);
+            B->ws_total = align_up(B->ws_total + need);
         }
         B->fp64 = plans[0]->fp64;
         bttb_status st = hip_check(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking), "stream create");

@@ -83,6 +83,9 @@ struct ColJob {
     int begin;            // first global block index of this job
     int px, py;           // real even spectra: phase offsets (pxl, pyl)
     int64_t lds;          // real even spectra: line stride (elements)
+    void* p;              // forward with ns > 1: FP64 partial depth sums,
+                          // [nrhs][ns][ncols][N] complex
+    int ns;               // forward: layer ranges (depth splits) per column block
 };
 struct ColJobs {
     ColJob j[MAX_JOBS];
@@ -118,6 +121,10 @@ hipError_t launch_cols_spec(int N, const double2* in, int ncols, int nl, void* s
                             double scale, const double2* tw, int form, int64_t ldr, hipStream_t s);
 template <typename T, int ACC>
 hipError_t launch_cols_fwd(int N, int tile, int form, const ColJobs& jobs, const cT<T>* tw, hipStream_t s);
+// sums the partial depth sums of jobs with ns > 1, then the forward's inverse
+// y transform and store (one block per column block and right-hand side)
+template <typename T>
+hipError_t launch_cols_fwd_fin(int N, int tile, int form, const ColJobs& jobs, const cT<T>* tw, hipStream_t s);
 template <typename T>
 hipError_t launch_cols_tr(int N, int tile, int form, const ColJobs& jobs, const cT<T>* tw, hipStream_t s);
 

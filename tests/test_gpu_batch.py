@@ -36,12 +36,23 @@ def test_batch48_equals_single_calls_and_replays(torch_cuda):
     ref_d = [p.forward(m) for p, m in zip(plans, ms)]
     ref_t = [p.transpose(r) for p, r in zip(plans, rs)]
     torch.cuda.synchronize()
+    first = None
     for rep in range(3):
         ds, mts = batch.run(ms, rs)
         torch.cuda.synchronize()
+        if first is None:
+            # the same products as single calls; a batch's forward launches
+            # hold more blocks and may split the depth sum less, which only
+            # regroups its FP64 partial sums (rounding of the FP32 result)
+            first = ([d.clone() for d in ds], [t.clone() for t in mts])
+            for k in range(len(plans)):
+                assert torch.equal(mts[k], ref_t[k]), k
+                assert rel_l2(ds[k].double().cpu().numpy().reshape(4, -1),
+                              ref_d[k].double().cpu().numpy().reshape(4, -1)) <= 1e-6, k
+        # every replay repeats the first bit for bit
         for k in range(len(plans)):
-            assert torch.equal(ds[k], ref_d[k]), (rep, k)
-            assert torch.equal(mts[k], ref_t[k]), (rep, k)
+            assert torch.equal(ds[k], first[0][k]), (rep, k)
+            assert torch.equal(mts[k], first[1][k]), (rep, k)
         # eager work between replays
         extra = plans[rep].forward(ms[rep])
         torch.cuda.synchronize()

@@ -355,3 +355,41 @@ def test_concurrent_calls_on_one_plan(torch_cuda):
     assert not errors, errors
     for k in range(4):
         assert torch.equal(outs[k][0], ref_d) and torch.equal(outs[k][1], ref_t)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("kind", [W.GRAVITY, W.MAGNETIC])
+def test_forward_depth_split_many_layers(torch_cuda, orc, prec, kind):
+    # few columns and 256 layers: the forward sums its layers in 64 ranges
+    # (FP64 partial sums added by the finishing kernel), for one and for
+    # several right-hand sides
+    kw = dict(dx=20.0, dy=20.0, dz=5.0)
+    if kind == W.MAGNETIC:
+        kw.update(incl=50.0, decl=-30.0, field_nT=47000.0)
+    pr = W.problem(kind, 6, 5, 256, 1, 2, 0, 1, **kw)
+    _say("depth split", kind, prec)
+    P = oracle_problem(pr)
+    G, A = orc.dense_G_quad(P, with_abs=True)
+    tq, _ = orc.offset_table_quad(P)
+    tol = TOL64 if prec == "fp64" else TOL32
+    eps = np.finfo(float).eps
+    plan = _plan(pr, prec)
+    from paper_1912_06976_amd import Plan
+    plan_t = Plan(dict(pr, kind=W.TABLE), prec)
+    plan_t.generate(table=torch_cuda.tensor(np.ascontiguousarray(tq), dtype=torch_cuda.float64, device="cuda"))
+    for nrhs in (1, 3):
+        m = W.normal_model(pr, 700 + nrhs, nrhs=nrhs)
+        v = W.normal_data(pr, 800 + nrhs, nrhs=nrhs)
+        # the exact entries as a table: the bar itself
+        d, t = _products(torch_cuda, plan_t, m, v)
+        assert rel_l2(d.reshape(nrhs, -1), m.reshape(nrhs, -1) @ G.T) <= tol
+        assert rel_l2(t.reshape(nrhs, -1), v.reshape(nrhs, -1) @ G) <= tol
+        # generated entries: the bar or the propagated entry bound (the
+        # deepest prisms are 64 cells below the stations)
+        d, t = _products(torch_cuda, plan, m, v)
+        for q in range(nrhs):
+            mq, vq = m[q].ravel(), v[q].ravel()
+            for got, ref, bnd in ((d[q].ravel(), G @ mq, 32 * eps * (A @ np.abs(mq))),
+                                  (t[q].ravel(), G.T @ vq, 32 * eps * (A.T @ np.abs(vq)))):
+                err, nref = np.linalg.norm(got - ref), np.linalg.norm(ref)
+                assert err <= max(tol * nref, np.linalg.norm(bnd) + 1e-13 * nref), err / nref
