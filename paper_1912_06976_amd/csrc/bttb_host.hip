@@ -222,14 +222,14 @@ struct WsLayout {
 
 // Layer ranges per column block of the forward MAC.  The kernel runs one
 // block per column block and right-hand side, each summing its layers in
-// turn; when a launch has few such blocks (`blocks`, over all its jobs) most
-// of the device would idle, so the layers are split into ranges (at least 4
-// layers each) until there are about two blocks per resident slot.  The
-// ranges' FP64 sums are added in range order by a finishing kernel.  The
+// turn; when a call has few such blocks (`blocks`, over all its products)
+// most of the device would idle, so the layers are split into ranges (at
+// least 4 layers each) until there are about two blocks per resident slot.
+// The ranges' FP64 sums are added in range order by a finishing kernel.  The
 // split, and with it the rounding, is a function of the plan, the
-// right-hand-side count and the launch's block count: repeated calls give
-// the same results; a batch, whose launches hold more blocks, may split less
-// than single calls and then differs from them by rounding.
+// right-hand-side count and the call's block count: repeated calls give the
+// same results; a batch, whose calls hold more blocks, may split less than
+// single calls and then differs from them by rounding.
 int fwd_split(const bttb_plan_s* P, int64_t blocks)
 {
     const int64_t target = P->fp64 ? 512 : 1024;
@@ -530,17 +530,11 @@ bttb_status run_forward(const std::vector<Item>& items, hipStream_t s, hipEvent_
 {
     RowStage<T> r1, r3;
     ColStage<T> c2, c2f;
-    // forward MAC blocks per column launch group (transform length, tile,
-    // form, accumulation), for the depth split
-    std::vector<std::pair<ColKey, int64_t>> group_blocks;
-    for (const Item& it : items) {
-        const bttb_plan_s* P = it.P;
-        const ColKey key{P->Ny, P->acc, P->col_tile, P->form};
-        size_t g = 0;
-        while (g < group_blocks.size() && !(group_blocks[g].first == key)) ++g;
-        if (g == group_blocks.size()) group_blocks.push_back({key, 0});
-        group_blocks[g].second += (int64_t)P->fwd_nbx * it.nrhs;
-    }
+    // forward MAC blocks of all items, for the depth split: the items of a
+    // batch branch run beside the other branches, which keep the device busy,
+    // so only a call with few blocks in all splits its layers
+    int64_t all_blocks = 0;
+    for (const Item& it : items) all_blocks += (int64_t)it.P->fwd_nbx * it.nrhs;
     for (const Item& it : items) {
         const bttb_plan_s* P = it.P;
         const WsLayout L = ws_layout(P, it.nrhs);
@@ -552,8 +546,7 @@ bttb_status run_forward(const std::vector<Item>& items, hipStream_t s, hipEvent_
                (int64_t)it.nrhs * P->nz);
         const ColKey key{P->Ny, P->acc, P->col_tile, P->form};
         ColJob cj = col_job(P, X, it.spec, Y, pny, psy, P->ny, P->sy, 0, P->nz, it.nrhs);
-        for (const auto& gb : group_blocks)
-            if (gb.first == key) cj.ns = fwd_split(P, gb.second);
+        cj.ns = fwd_split(P, all_blocks);
         cj.p = it.ws + L.fwd_p;
         c2.add(key, tw_y<T>(P, it.spec), cj, cj.ns);
         if (cj.ns > 1) c2f.add(ColKey{P->Ny, 0, P->col_tile, P->form}, tw_y<T>(P, it.spec), cj);
