@@ -189,7 +189,12 @@ bttb_status bttb_kernel_generate_table(bttb_plan_t plan, const double* table, vo
  * m: device [nrhs][nz][ny][nx]; d: device [nrhs][sy][sx]; workspace >=
  * workspace_bytes of bttb_plan_query(plan, nrhs, ...).  m and d must not
  * overlap the workspace.  Errors: NULL_POINTER, INVALID_VALUE (nrhs < 1),
- * WORKSPACE_TOO_SMALL, HIP. */
+ * WORKSPACE_TOO_SMALL, HIP.
+ * Results are deterministic for a given plan and nrhs.  When a call has few
+ * column blocks, the depth sum is split into layer ranges whose FP64 partial
+ * sums are added in order.  The split depends on nrhs, and for a batch on
+ * the other problems of its branch.  A different nrhs or a batch may
+ * therefore round the FP32 result differently, within its accuracy. */
 bttb_status bttb_forward(bttb_plan_t plan, const void* spectra, const void* m, void* d,
                          int32_t nrhs, void* workspace, size_t ws_bytes, void* stream);
 
