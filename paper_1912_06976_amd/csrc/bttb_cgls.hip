@@ -105,15 +105,25 @@ __global__ void __launch_bounds__(RED_THREADS) k_residual(const T* __restrict__ 
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
-// s = s - lambda^2 m; partials of ||s||^2 (out_s) and ||m||^2 (out_m)
+// with step: m = m + alpha p (alpha from the scalars); then s = s - lambda^2 m;
+// partials of ||s||^2 (out_s) and ||m||^2 (out_m).  The step of m is done
+// here rather than beside r's (k_step): the transpose product between them
+// reads r only, and one pass over m, p and s saves a pass over m.
 template <typename T>
-__global__ void __launch_bounds__(RED_THREADS) k_grad(T* __restrict__ s, const T* __restrict__ m, double lam2,
+__global__ void __launch_bounds__(RED_THREADS) k_grad(T* __restrict__ s, T* __restrict__ m, const T* __restrict__ p,
+                                                      const CglsScalars* __restrict__ sc, int step, double lam2,
                                                       int64_t n, double* __restrict__ out_s, double* __restrict__ out_m)
 {
+    const double alpha = step ? sc->alpha : 0.0;
     double vs = 0.0, vm = 0.0;
-    BTTB_GRID_LOOPS(n, al16(s) && al16(m), {
+    BTTB_GRID_LOOPS(n, al16(s) && al16(m) && (!step || al16(p)), {
         V4<T> sv = ld4(s + i);
-        const V4<T> mv = ld4(m + i);
+        V4<T> mv = ld4((const T*)m + i);
+        if (step) {
+            const V4<T> pv = ld4(p + i);
+            for (int k = 0; k < 4; ++k) mv.x[k] = (T)((double)mv.x[k] + alpha * (double)pv.x[k]);
+            st4(m + i, mv);
+        }
         for (int k = 0; k < 4; ++k) {
             sv.x[k] = (T)((double)sv.x[k] - lam2 * (double)mv.x[k]);
             vs += (double)sv.x[k] * (double)sv.x[k];
@@ -121,7 +131,11 @@ __global__ void __launch_bounds__(RED_THREADS) k_grad(T* __restrict__ s, const T
         }
         st4(s + i, sv);
     }, {
-        const T mi = m[i];
+        T mi = m[i];
+        if (step) {
+            mi = (T)((double)mi + alpha * (double)p[i]);
+            m[i] = mi;
+        }
         const T x = (T)((double)s[i] - lam2 * (double)mi);
         s[i] = x;
         vs += (double)x * (double)x;
@@ -162,22 +176,13 @@ __global__ void __launch_bounds__(RED_THREADS) k_direction(const T* __restrict__
     if (threadIdx.x == 0) out[blockIdx.x] = a;
 }
 
-// m = m + alpha p over [0, n); r = r - alpha q over [0, nd); partials of
-// ||r||^2 after the update (blocks past the m range do r)
+// r = r - alpha q over [0, nd); partials of ||r||^2 after the update (the
+// matching step of m is done by k_grad)
 template <typename T>
-__global__ void __launch_bounds__(RED_THREADS) k_step(T* __restrict__ m, const T* __restrict__ p, int64_t n,
-                                                      T* __restrict__ r, const T* __restrict__ q, int64_t nd,
+__global__ void __launch_bounds__(RED_THREADS) k_step(T* __restrict__ r, const T* __restrict__ q, int64_t nd,
                                                       const CglsScalars* __restrict__ sc, double* __restrict__ out)
 {
     const double alpha = sc->alpha;
-    BTTB_GRID_LOOPS(n, al16(m) && al16(p), {
-        V4<T> mv = ld4((const T*)m + i);
-        const V4<T> pv = ld4(p + i);
-        for (int k = 0; k < 4; ++k) mv.x[k] = (T)((double)mv.x[k] + alpha * (double)pv.x[k]);
-        st4(m + i, mv);
-    }, {
-        m[i] = (T)((double)m[i] + alpha * (double)p[i]);
-    })
     double v = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < nd; i += (int64_t)gridDim.x * RED_THREADS) {
         const T x = (T)((double)r[i] - alpha * (double)q[i]);
@@ -237,10 +242,10 @@ hipError_t launch_cgls_residual(const T* d, const T* q, T* r, int64_t n, double*
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_cgls_grad(T* sv, const T* m, double lam2, int64_t n, double* out_s, double* out_m, int nb,
-                            hipStream_t s)
+hipError_t launch_cgls_grad(T* sv, T* m, const T* p, const CglsScalars* sc, int step, double lam2, int64_t n,
+                            double* out_s, double* out_m, int nb, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_grad<T>, dim3(nb), dim3(RED_THREADS), 0, s, sv, m, lam2, n, out_s, out_m);
+    hipLaunchKernelGGL(k_grad<T>, dim3(nb), dim3(RED_THREADS), 0, s, sv, m, p, sc, step, lam2, n, out_s, out_m);
     return hipGetLastError();
 }
 template <typename T>
@@ -251,10 +256,9 @@ hipError_t launch_cgls_direction(const T* sv, T* p, int64_t n, const CglsScalars
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_cgls_step(T* m, const T* p, int64_t n, T* r, const T* q, int64_t nd, const CglsScalars* sc,
-                            double* out, int nb, hipStream_t s)
+hipError_t launch_cgls_step(T* r, const T* q, int64_t nd, const CglsScalars* sc, double* out, int nb, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_step<T>, dim3(nb), dim3(RED_THREADS), 0, s, m, p, n, r, q, nd, sc, out);
+    hipLaunchKernelGGL(k_step<T>, dim3(nb), dim3(RED_THREADS), 0, s, r, q, nd, sc, out);
     return hipGetLastError();
 }
 hipError_t launch_cgls_alpha(const double* pq, const double* pp, int nb, double lam2, CglsScalars* sc, hipStream_t s)
@@ -272,11 +276,11 @@ hipError_t launch_cgls_beta(const double* ps, const double* pr, const double* pm
 #define BTTB_CGLS_INST(T)                                                                                   \
     template hipError_t launch_cgls_dot<T>(const T*, const T*, int64_t, double*, int, hipStream_t);         \
     template hipError_t launch_cgls_residual<T>(const T*, const T*, T*, int64_t, double*, int, hipStream_t); \
-    template hipError_t launch_cgls_grad<T>(T*, const T*, double, int64_t, double*, double*, int, hipStream_t); \
+    template hipError_t launch_cgls_grad<T>(T*, T*, const T*, const CglsScalars*, int, double, int64_t, double*, \
+                                            double*, int, hipStream_t);                                     \
     template hipError_t launch_cgls_direction<T>(const T*, T*, int64_t, const CglsScalars*, int, double*, int, \
                                                  hipStream_t);                                              \
-    template hipError_t launch_cgls_step<T>(T*, const T*, int64_t, T*, const T*, int64_t, const CglsScalars*, \
-                                            double*, int, hipStream_t);
+    template hipError_t launch_cgls_step<T>(T*, const T*, int64_t, const CglsScalars*, double*, int, hipStream_t);
 BTTB_CGLS_INST(float)
 BTTB_CGLS_INST(double)
 #undef BTTB_CGLS_INST

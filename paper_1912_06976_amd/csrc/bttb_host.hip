@@ -682,16 +682,17 @@ bttb_status run_cgls(const bttb_plan_s* P, const char* spec, const T* d, T* m, d
     CG(run_single<T>(true, P, spec, m, q, 1, wp, st), "forward");
     CGH(launch_cgls_residual<T>(d, q, r, L.nd, pr, nb, st), "cgls residual");
     CG(run_single<T>(false, P, spec, r, sv, 1, wp, st), "transpose");
-    CGH(launch_cgls_grad<T>(sv, m, lam2, L.n, ps, pm, nb, st), "cgls gradient");
+    CGH(launch_cgls_grad<T>(sv, m, p, sc, 0, lam2, L.n, ps, pm, nb, st), "cgls gradient");
     CGH(launch_cgls_beta(ps, pr, pm, nb, sc, hist, 0, 1, st), "cgls scalars");
     CGH(launch_cgls_direction<T>(sv, p, L.n, sc, 1, pp, nb, st), "cgls direction");
     for (int k = 1; k <= iters; ++k) {
         CG(run_single<T>(true, P, spec, p, q, 1, wp, st), "forward");
         CGH(launch_cgls_dot<T>(q, q, L.nd, pq, nb, st), "cgls dot");
         CGH(launch_cgls_alpha(pq, pp, nb, lam2, sc, st), "cgls scalars");
-        CGH(launch_cgls_step<T>(m, p, L.n, r, q, L.nd, sc, pr, nb, st), "cgls step");
+        CGH(launch_cgls_step<T>(r, q, L.nd, sc, pr, nb, st), "cgls step");
         CG(run_single<T>(false, P, spec, r, sv, 1, wp, st), "transpose");
-        CGH(launch_cgls_grad<T>(sv, m, lam2, L.n, ps, pm, nb, st), "cgls gradient");
+        // m += alpha p with s = G^T r - lambda^2 m (one pass over m, p, s)
+        CGH(launch_cgls_grad<T>(sv, m, p, sc, 1, lam2, L.n, ps, pm, nb, st), "cgls gradient");
         CGH(launch_cgls_beta(ps, pr, pm, nb, sc, hist, k, 0, st), "cgls scalars");
         CGH(launch_cgls_direction<T>(sv, p, L.n, sc, 0, pp, nb, st), "cgls direction");
     }

@@ -133,14 +133,13 @@ template <typename T> hipError_t launch_cgls_dot(const T* a, const T* b, int64_t
 template <typename T>
 hipError_t launch_cgls_residual(const T* d, const T* q, T* r, int64_t n, double* out, int nb, hipStream_t s);
 template <typename T>
-hipError_t launch_cgls_grad(T* sv, const T* m, double lam2, int64_t n, double* out_s, double* out_m, int nb,
-                            hipStream_t s);
+hipError_t launch_cgls_grad(T* sv, T* m, const T* p, const CglsScalars* sc, int step, double lam2, int64_t n,
+                            double* out_s, double* out_m, int nb, hipStream_t s);
 template <typename T>
 hipError_t launch_cgls_direction(const T* sv, T* p, int64_t n, const CglsScalars* sc, int first, double* out, int nb,
                                  hipStream_t s);
 template <typename T>
-hipError_t launch_cgls_step(T* m, const T* p, int64_t n, T* r, const T* q, int64_t nd, const CglsScalars* sc,
-                            double* out, int nb, hipStream_t s);
+hipError_t launch_cgls_step(T* r, const T* q, int64_t nd, const CglsScalars* sc, double* out, int nb, hipStream_t s);
 hipError_t launch_cgls_alpha(const double* pq, const double* pp, int nb, double lam2, CglsScalars* sc, hipStream_t s);
 hipError_t launch_cgls_beta(const double* ps, const double* pr, const double* pm, int nb, CglsScalars* sc,
                             double* hist, int k, int first, hipStream_t s);
