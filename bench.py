@@ -12,8 +12,9 @@ steps in one timed region) it reports the mean, median and extremes of single
 steps, the FP64 path, the kernel-generation time, per-kernel times from HIP
 events recorded on the launch stream, the roofline of the dominant kernel
 (against the 8 TB/s HBM peak and against the rate of a plain device copy
-measured in the same run), and the CPU oracle's rate on a bounded sample of
-the same workload.
+measured in the same run), the CPU oracle's rate on a bounded sample of
+the same workload, and, as context, the per-layer FFT method on the host
+cores with scipy.fft (the paper's FFTW approach).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -202,6 +203,46 @@ def copy_rate(torch, nbytes=1 << 30, reps=10):
     del src, dst
     torch.cuda.empty_cache()
     return round(gbs, 1)
+
+
+def cpu_fft_context(pr, nlayers, workers):
+    """Context only (not the oracle, not the target): the per-layer FFT
+    method as the paper runs it with FFTW, here scipy.fft on the host cores.
+    Spectra of `nlayers` layers (synthetic values: the time does not depend
+    on them) are precomputed; one G m + G^T r over those layers is timed and
+    scaled to all nz layers.  FP64 and FP32."""
+    import scipy.fft as sf
+    nx, ny, nz = W.dims(pr)
+    sx, sy = pr["sx"], pr["sy"]
+
+    def p2(n):
+        v = 8
+        while v < n:
+            v *= 2
+        return v
+    Nx, Ny = p2(sx + nx - 1), p2(sy + ny - 1)
+    out = {"workers": workers, "layers_timed": nlayers, "fft": "%dx%d" % (Nx, Ny)}
+    for name, dt, cdt in (("fp64", np.float64, np.complex128), ("fp32", np.float32, np.complex64)):
+        rng = np.random.default_rng(11)
+        that = (rng.standard_normal((nlayers, Ny, Nx // 2 + 1))
+                + 1j * rng.standard_normal((nlayers, Ny, Nx // 2 + 1))).astype(cdt)
+        m = rng.standard_normal((nlayers, ny, nx)).astype(dt)
+        r = rng.standard_normal((sy, sx)).astype(dt)
+
+        def pair():
+            acc = np.zeros((Ny, Nx // 2 + 1), dtype=cdt)
+            for k in range(nlayers):
+                acc += that[k] * sf.rfft2(m[k], s=(Ny, Nx), workers=workers)
+            d = sf.irfft2(acc, s=(Ny, Nx), workers=workers)[:sy, :sx]
+            rh = sf.rfft2(r, s=(Ny, Nx), workers=workers)
+            mt = [sf.irfft2(np.conj(that[k]) * rh, s=(Ny, Nx), workers=workers)[:ny, :nx] for k in range(nlayers)]
+            return d, mt
+        pair()
+        t0 = time.perf_counter()
+        pair()
+        t = (time.perf_counter() - t0) * nz / nlayers
+        out[name] = {"ms_per_pair": round(t * 1e3, 1), "cells_per_s": nx * ny * nz / t}
+    return out
 
 
 def run_batch(torch, B, steps):
@@ -464,6 +505,8 @@ def main():
             "value": cells / t_pair, "unit": "cells/s", "cores": threads, "kind": "oracle",
             "sample": "direct sums (no FFT) of G m at %d stations and G^T r at %d prisms of the same "
                       "workload, %.1f s, extrapolated to one full G m + G^T r" % (len(st), len(pq), t2 - t0)}
+        log("cpu FFT context (scipy.fft)")
+        result["cpu_fft_context"] = cpu_fft_context(pr, 8, threads)
         gi = np.array([d32[j, i] for (i, j) in st])
         gt = np.array([mt32[r, q, p] for (p, q, r) in pq])
         result["parity_sample_rel_l2"] = {
