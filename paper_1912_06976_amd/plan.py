@@ -245,7 +245,10 @@ class Plan:
         nrhs = self._check_vec(m, (self.nz, self.ny, self.nx), "m")
         if out is None:
             out = torch.empty(m.shape[:-3] + (self.sy, self.sx), dtype=self.dtype, device=m.device)
-        self._check_vec(out, (self.sy, self.sx), "out")
+        if self._check_vec(out, (self.sy, self.sx), "out") != nrhs:
+            raise ValueError("out holds a different number of right-hand sides than m")
+        if nrhs == 0:
+            return out
         bttb_forward(self.handle, self.spectra, m, out, nrhs, self.workspace(nrhs), stream)
         return out
 
@@ -255,7 +258,10 @@ class Plan:
         nrhs = self._check_vec(r, (self.sy, self.sx), "r")
         if out is None:
             out = torch.empty(r.shape[:-2] + (self.nz, self.ny, self.nx), dtype=self.dtype, device=r.device)
-        self._check_vec(out, (self.nz, self.ny, self.nx), "out")
+        if self._check_vec(out, (self.nz, self.ny, self.nx), "out") != nrhs:
+            raise ValueError("out holds a different number of right-hand sides than r")
+        if nrhs == 0:
+            return out
         bttb_transpose(self.handle, self.spectra, r, out, nrhs, self.workspace(nrhs), stream)
         return out
 

@@ -393,3 +393,22 @@ def test_forward_depth_split_many_layers(torch_cuda, orc, prec, kind):
                                   (t[q].ravel(), G.T @ vq, 32 * eps * (A.T @ np.abs(vq)))):
                 err, nref = np.linalg.norm(got - ref), np.linalg.norm(ref)
                 assert err <= max(tol * nref, np.linalg.norm(bnd) + 1e-13 * nref), err / nref
+
+
+def test_empty_inputs_and_rhs_mismatch(torch_cuda):
+    # no right-hand side: empty results, nothing launched; an output with a
+    # different right-hand-side count is refused before any launch
+    torch = torch_cuda
+    pr = W.small_gravity()
+    plan = _plan(pr, "fp32")
+    m0 = torch.empty((0, plan.nz, plan.ny, plan.nx), device="cuda")
+    r0 = torch.empty((0, plan.sy, plan.sx), device="cuda")
+    assert tuple(plan.forward(m0).shape) == (0, plan.sy, plan.sx)
+    assert tuple(plan.transpose(r0).shape) == (0, plan.nz, plan.ny, plan.nx)
+    m2 = torch.zeros((2, plan.nz, plan.ny, plan.nx), device="cuda")
+    r2 = torch.zeros((2, plan.sy, plan.sx), device="cuda")
+    with pytest.raises(ValueError):
+        plan.forward(m2, out=torch.empty((3, plan.sy, plan.sx), device="cuda"))
+    with pytest.raises(ValueError):
+        plan.transpose(r2, out=torch.empty((1, plan.nz, plan.ny, plan.nx), device="cuda"))
+    torch.cuda.synchronize()
