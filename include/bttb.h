@@ -187,9 +187,10 @@ bttb_status bttb_kernel_generate_table(bttb_plan_t plan, const double* table, vo
 
 /* d = G m for nrhs right-hand sides (the paper's mult_BTTB with t = 1).
  * m: device [nrhs][nz][ny][nx]; d: device [nrhs][sy][sx]; workspace >=
- * workspace_bytes of bttb_plan_query(plan, nrhs, ...).  m and d must not
- * overlap the workspace.  Errors: NULL_POINTER, INVALID_VALUE (nrhs < 1),
- * WORKSPACE_TOO_SMALL, HIP.
+ * workspace_bytes of bttb_plan_query(plan, nrhs, ...).  m, d and the
+ * spectra must not overlap the workspace, nor d the spectra (checked:
+ * INVALID_VALUE).  Errors: NULL_POINTER, INVALID_VALUE (nrhs < 1, a
+ * misaligned buffer or an overlap), WORKSPACE_TOO_SMALL, HIP.
  * Results are deterministic for a given plan and nrhs.  When a call has few
  * column blocks, the depth sum is split into layer ranges whose FP64 partial
  * sums are added in order.  The split depends on nrhs, and for a batch on
@@ -199,7 +200,8 @@ bttb_status bttb_forward(bttb_plan_t plan, const void* spectra, const void* m, v
                          int32_t nrhs, void* workspace, size_t ws_bytes, void* stream);
 
 /* mt = G^T r for nrhs right-hand sides (mult_BTTB with t = 2).
- * r: device [nrhs][sy][sx]; mt: device [nrhs][nz][ny][nx]. */
+ * r: device [nrhs][sy][sx]; mt: device [nrhs][nz][ny][nx].  Workspace,
+ * overlap rules and errors as for bttb_forward. */
 bttb_status bttb_transpose(bttb_plan_t plan, const void* spectra, const void* r, void* mt,
                            int32_t nrhs, void* workspace, size_t ws_bytes, void* stream);
 

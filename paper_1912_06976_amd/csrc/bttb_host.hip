@@ -788,17 +788,39 @@ bttb_status bttb_kernel_generate_table(bttb_plan_t plan, const double* table, vo
     }
 }
 
+static bool overlap(const void* a, size_t na, const void* b, size_t nb)
+{
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+// in_elems / out_elems: elements per right-hand side of the input and output
 static bttb_status check_product_args(bttb_plan_t plan, const void* spectra, const void* in, void* out,
-                                      int32_t nrhs, void* workspace, size_t ws_bytes)
+                                      int32_t nrhs, void* workspace, size_t ws_bytes, size_t in_elems,
+                                      size_t out_elems)
 {
     if (!plan || !spectra || !in || !out || !workspace)
         return fail(BTTB_ERR_NULL_POINTER, "plan, spectra, input, output and workspace must not be NULL");
     if (nrhs < 1) return fail(BTTB_ERR_INVALID_VALUE, "nrhs must be >= 1");
     if (!aligned(spectra, kAlign) || !aligned(workspace, 16) || !aligned(in, plan->esz) || !aligned(out, plan->esz))
         return fail(BTTB_ERR_INVALID_VALUE, "misaligned buffer (spectra 256 B, workspace 16 B, vectors element size)");
-    if (ws_bytes < ws_layout(plan, nrhs).total)
+    const size_t need = ws_layout(plan, nrhs).total;
+    if (ws_bytes < need)
         return fail(BTTB_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than bttb_plan_query(plan, nrhs) reports");
+    if (overlap(in, (size_t)nrhs * in_elems * plan->esz, workspace, need) ||
+        overlap(out, (size_t)nrhs * out_elems * plan->esz, workspace, need) ||
+        overlap(spectra, plan->spec_bytes, workspace, need) ||
+        overlap(out, (size_t)nrhs * out_elems * plan->esz, spectra, plan->spec_bytes))
+        return fail(BTTB_ERR_INVALID_VALUE, "the input, output and spectra must not overlap the workspace, "
+                                            "nor the output the spectra");
     return BTTB_OK;
+}
+static bttb_status check_product(bool fwd, bttb_plan_t plan, const void* spectra, const void* in, void* out,
+                                 int32_t nrhs, void* workspace, size_t ws_bytes)
+{
+    if (!plan) return fail(BTTB_ERR_NULL_POINTER, "plan must not be NULL");
+    const size_t nm = (size_t)plan->nx * plan->ny * plan->nz, nd = (size_t)plan->sx * plan->sy;
+    return check_product_args(plan, spectra, in, out, nrhs, workspace, ws_bytes, fwd ? nm : nd, fwd ? nd : nm);
 }
 
 bttb_status bttb_forward(bttb_plan_t plan, const void* spectra, const void* m, void* d, int32_t nrhs,
@@ -806,7 +828,7 @@ bttb_status bttb_forward(bttb_plan_t plan, const void* spectra, const void* m, v
 {
     try {
         g_last_error.clear();
-        bttb_status st = check_product_args(plan, spectra, m, d, nrhs, workspace, ws_bytes);
+        bttb_status st = check_product(true, plan, spectra, m, d, nrhs, workspace, ws_bytes);
         if (st != BTTB_OK) return st;
         hipStream_t s = (hipStream_t)stream;
         return plan->fp64 ? run_single<double>(true, plan, (const char*)spectra, m, d, nrhs, (char*)workspace, s)
@@ -821,7 +843,7 @@ bttb_status bttb_transpose(bttb_plan_t plan, const void* spectra, const void* r,
 {
     try {
         g_last_error.clear();
-        bttb_status st = check_product_args(plan, spectra, r, mt, nrhs, workspace, ws_bytes);
+        bttb_status st = check_product(false, plan, spectra, r, mt, nrhs, workspace, ws_bytes);
         if (st != BTTB_OK) return st;
         hipStream_t s = (hipStream_t)stream;
         return plan->fp64 ? run_single<double>(false, plan, (const char*)spectra, r, mt, nrhs, (char*)workspace, s)
@@ -834,7 +856,7 @@ bttb_status bttb_transpose(bttb_plan_t plan, const void* spectra, const void* r,
 static bttb_status profiled(bool fwd, bttb_plan_t plan, const void* spectra, const void* in, void* out,
                             int32_t nrhs, void* workspace, size_t ws_bytes, void* stream, float* kernel_ms)
 {
-    bttb_status st = check_product_args(plan, spectra, in, out, nrhs, workspace, ws_bytes);
+    bttb_status st = check_product(fwd, plan, spectra, in, out, nrhs, workspace, ws_bytes);
     if (st != BTTB_OK) return st;
     if (!kernel_ms) return fail(BTTB_ERR_NULL_POINTER, "kernel_ms must not be NULL");
     hipStream_t s = (hipStream_t)stream;

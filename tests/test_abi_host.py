@@ -184,6 +184,26 @@ def test_workspace_too_small_is_rejected_before_launch(lib):
     B.bttb_plan_destroy(h)
 
 
+def test_overlapping_buffers_are_rejected(lib):
+    # fake (never dereferenced) device pointers: the overlap check fails
+    # before anything is enqueued
+    import paper_1912_06976_amd as B
+    h = B.bttb_plan_create(W.small_gravity(), "fp64")
+    sb, wb, _, _ = B.bttb_plan_query(h, 1)
+    assert sb < (1 << 28) and wb < (1 << 28)
+    base = 1 << 32
+    spec, ws, far = base, base + (1 << 28), base + (1 << 29)
+    P = ctypes.c_void_p
+    # input inside the workspace
+    assert lib.bttb_forward(P(h), P(spec), P(ws + 256), P(far), 1, P(ws), wb, None) == 1
+    # output inside the workspace
+    assert lib.bttb_transpose(P(h), P(spec), P(far), P(ws + 512), 1, P(ws), wb, None) == 1
+    # output over the spectra
+    assert lib.bttb_transpose(P(h), P(spec), P(far), P(spec + 256), 1, P(ws), wb, None) == 1
+    assert "overlap" in lib.bttb_last_error().decode()
+    B.bttb_plan_destroy(h)
+
+
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     from paper_1912_06976_amd import _lib
     monkeypatch.setattr(_lib, "_handle", None)
