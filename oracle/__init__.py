@@ -80,8 +80,9 @@ _lib_handle = None
 def _lib():
     global _lib_handle
     if _lib_handle is None:
-        build()
-        L = ctypes.CDLL(_LIB)
+        # ORACLE_LIB: an instrumented build of the same source (sanitizer test)
+        path = os.environ.get("ORACLE_LIB") or build()
+        L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int32)
         pp = ctypes.POINTER(_Problem)
