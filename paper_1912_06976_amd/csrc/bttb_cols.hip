@@ -4,7 +4,9 @@
 //
 //   k_cols_fwd_mac   forward product: per column kx, the depth loop
 //                    A += T^_r * FFT_y(X_r) with an extended accumulator, then
-//                    one inverse FFT_y
+//                    one inverse FFT_y (or, with the layers split into ranges,
+//                    the range's FP64 sum)
+//   k_cols_fwd_fin   adds the ranges' sums in order and finishes the column
 //   k_cols_tr_mac    transpose product: R^ = FFT_y(R) once per column, then per
 //                    layer IFFT_y(conj(T^_r) R^)
 //
