@@ -112,11 +112,25 @@ def pair_bytes(pr, Nx, Ny, esz, form):
 KERNEL_SOURCES = ["bttb_kernels.hip", "bttb_cols.hip", "fft_core.h", "kern_common.h", "bttb_internal.h"]
 
 
+def kernel_source_hash():
+    """SHA-256 of the kernel sources with comments and whitespace removed, so
+    that edits of comments alone do not retire measured counters."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1912_06976_amd", "csrc")
+    for f in KERNEL_SOURCES:
+        text = open(os.path.join(csrc, f), encoding="utf-8").read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(re.sub(r"\s+", " ", text).strip().encode())
+    return h.hexdigest()
+
+
 def counter_traffic(kernel):
     """Scaled HBM bytes (FETCH_SIZE + WRITE_SIZE, rocprofv3 PMC runs) of one
     launch of `kernel`, from the committed profile summary -- only if the
     kernel sources are unchanged since the counters were taken, else None."""
-    import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "hbm_counters_gravity_1024_fp32.md")
     if not os.path.exists(path):
@@ -125,11 +139,7 @@ def counter_traffic(kernel):
     if not m:
         return None
     info = json.loads(m.group(1))
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1912_06976_amd", "csrc")
-    for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(csrc, f), "rb").read())
-    if h.hexdigest() != info.get("source_sha256"):
+    if kernel_source_hash() != info.get("source_sha256"):
         return None
     k = info.get("kernels", {}).get(kernel)
     return None if k is None else k["read_bytes"] + k["write_bytes"]
