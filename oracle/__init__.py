@@ -15,7 +15,8 @@ eq. continuousforwardmodel / eq. Gslice of Hogue, Renaut & Vatankhah):
                       dense matrix (Sec. 5: the direct products the paper
                       compares against);
 * ``station_sums`` / ``prism_sums`` -- single rows / columns of G m and G^T r
-                      for volumes too large for a dense G;
+                      for volumes too large for a dense G, in double or (quad)
+                      entirely in __float128;
 * ``regularized_lsq`` -- the minimiser of ||G m - d||^2 + lam^2 ||m||^2 from
                       the dense normal equations (checks the inversion driver);
 * ``dense_from_table`` -- dense G of a kernel given by its entries per layer
@@ -99,6 +100,10 @@ def _lib():
         L.orc_station_sums.argtypes = [pp, dp, ctypes.c_int, ip, dp]
         L.orc_prism_sums.restype = ctypes.c_int
         L.orc_prism_sums.argtypes = [pp, dp, ctypes.c_int, ip, dp]
+        L.orc_station_sums_quad.restype = ctypes.c_int
+        L.orc_station_sums_quad.argtypes = [pp, dp, ctypes.c_int, ip, dp]
+        L.orc_prism_sums_quad.restype = ctypes.c_int
+        L.orc_prism_sums_quad.argtypes = [pp, dp, ctypes.c_int, ip, dp]
         _lib_handle = L
     return _lib_handle
 
@@ -257,25 +262,31 @@ def transpose(G: np.ndarray, v: np.ndarray) -> np.ndarray:
     return v.reshape(-1, G.shape[0]) @ G
 
 
-def station_sums(P: Problem, m: np.ndarray, stations) -> np.ndarray:
-    """(G m)[k] at the given (i, j) stations without forming G; m is [nz][ny][nx]."""
+def station_sums(P: Problem, m: np.ndarray, stations, quad: bool = False) -> np.ndarray:
+    """(G m)[k] at the given (i, j) stations without forming G; m is [nz][ny][nx].
+    quad: corner terms and sums in __float128, rounded once (the exact reference)."""
     mm = np.ascontiguousarray(m, dtype=np.float64).reshape(P.nz, P.ny, P.nx)
     ij = np.ascontiguousarray(np.asarray(stations, dtype=np.int32).reshape(-1, 2))
     out = np.empty(ij.shape[0], dtype=np.float64)
     ps = P.c_struct()
-    rc = _lib().orc_station_sums(ctypes.byref(ps), _dptr(mm), ij.shape[0], _iptr(ij), _dptr(out))
+    fn = _lib().orc_station_sums_quad if quad else _lib().orc_station_sums
+    rc = fn(ctypes.byref(ps), _dptr(mm), ij.shape[0], _iptr(ij), _dptr(out))
     if rc != 0:
-        raise MemoryError("orc_station_sums failed")
+        raise RuntimeError("orc_station_sums failed (%d)" % rc)
     return out
 
 
-def prism_sums(P: Problem, v: np.ndarray, prisms) -> np.ndarray:
-    """(G^T v)[l] at the given (p, q, r) prisms without forming G; v is [sy][sx]."""
+def prism_sums(P: Problem, v: np.ndarray, prisms, quad: bool = False) -> np.ndarray:
+    """(G^T v)[l] at the given (p, q, r) prisms without forming G; v is [sy][sx].
+    quad: entries and sums in __float128, rounded once (the exact reference)."""
     vv = np.ascontiguousarray(v, dtype=np.float64).reshape(P.sy, P.sx)
     pqr = np.ascontiguousarray(np.asarray(prisms, dtype=np.int32).reshape(-1, 3))
     out = np.empty(pqr.shape[0], dtype=np.float64)
     ps = P.c_struct()
-    _lib().orc_prism_sums(ctypes.byref(ps), _dptr(vv), pqr.shape[0], _iptr(pqr), _dptr(out))
+    fn = _lib().orc_prism_sums_quad if quad else _lib().orc_prism_sums
+    rc = fn(ctypes.byref(ps), _dptr(vv), pqr.shape[0], _iptr(pqr), _dptr(out))
+    if rc != 0:
+        raise RuntimeError("orc_prism_sums failed (%d)" % rc)
     return out
 
 

@@ -320,3 +320,99 @@ int orc_prism_sums(const orc_problem *P, const double *v, int np, const int32_t 
     }
     return 0;
 }
+
+/*
+ * The same direct sums with every corner term, entry and partial sum in
+ * __float128, rounded to double once at the end: the exact reference for
+ * sampled outputs of volumes too large for a dense matrix.  Partial sums are
+ * kept per row of the corner grid (per station row for prisms) and added in
+ * row order, so the result does not depend on the thread count.
+ */
+int orc_station_sums_quad(const orc_problem *P, const double *m, int ns, const int32_t *ij, double *out)
+{
+    const int nx = orc_nx(P), ny = orc_ny(P);
+    if (P->kind == 2) return 2;
+    __float128 g[5] = {0, 0, 0, 0, 0};
+    if (P->kind == 1) orc_mag_weights_q(P->incl, P->decl, g);
+    const int64_t ce = (int64_t)(nx + 1) * (ny + 1);
+    __float128 *lo = (__float128 *)malloc(sizeof(__float128) * ce);
+    __float128 *hi = (__float128 *)malloc(sizeof(__float128) * ce);
+    __float128 *part = (__float128 *)malloc(sizeof(__float128) * ny);
+    if (!lo || !hi || !part) { free(lo); free(hi); free(part); return 1; }
+    const __float128 scale = P->scale;
+    for (int s = 0; s < ns; ++s) {
+        const int i = ij[2 * s], j = ij[2 * s + 1];
+        const __float128 a = ((__float128)i + 0.5Q) * P->dx, bb = ((__float128)j + 0.5Q) * P->dy;
+        __float128 acc = 0;
+        for (int r = 0; r < P->nz; ++r) {
+            for (int half = 0; half < 2; ++half) {
+                __float128 *dst = half ? hi : lo;
+                if (half == 0 && r > 0) { memcpy(lo, hi, sizeof(__float128) * ce); continue; }
+                const __float128 zeta = (__float128)P->zedge[r + half] + P->h;
+#pragma omp parallel for schedule(dynamic, 4)
+                for (int f = 0; f <= ny; ++f) {
+                    const __float128 ups = (__float128)(f - P->pyl) * P->dy - bb;
+                    for (int e = 0; e <= nx; ++e) {
+                        const __float128 chi = (__float128)(e - P->pxl) * P->dx - a;
+                        dst[(int64_t)f * (nx + 1) + e] = (P->kind == 0)
+                            ? orc_grav_corner_q(chi, ups, zeta)
+                            : orc_mag_corner_q(chi, ups, zeta, g);
+                    }
+                }
+            }
+#pragma omp parallel for schedule(static)
+            for (int q = 0; q < ny; ++q) {
+                __float128 rowsum = 0;
+                for (int p = 0; p < nx; ++p) {
+                    const int64_t c00 = (int64_t)q * (nx + 1) + p, c01 = c00 + 1;
+                    const int64_t c10 = c00 + (nx + 1), c11 = c10 + 1;
+                    const __float128 sum = -lo[c00] + lo[c01] + lo[c10] - lo[c11]
+                                           + hi[c00] - hi[c01] - hi[c10] + hi[c11];
+                    rowsum += scale * sum * (__float128)m[(int64_t)r * nx * ny + (int64_t)q * nx + p];
+                }
+                part[q] = rowsum;
+            }
+            for (int q = 0; q < ny; ++q) acc += part[q];
+        }
+        out[s] = (double)acc;
+    }
+    free(lo);
+    free(hi);
+    free(part);
+    return 0;
+}
+
+int orc_prism_sums_quad(const orc_problem *P, const double *v, int np, const int32_t *pqr, double *out)
+{
+    if (P->kind == 2) return 2;
+    __float128 g[5] = {0, 0, 0, 0, 0};
+    if (P->kind == 1) orc_mag_weights_q(P->incl, P->decl, g);
+    __float128 *part = (__float128 *)malloc(sizeof(__float128) * P->sy);
+    if (!part) return 1;
+    for (int s = 0; s < np; ++s) {
+        const int p = pqr[3 * s], q = pqr[3 * s + 1], r = pqr[3 * s + 2];
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int j = 0; j < P->sy; ++j) {
+            __float128 rowsum = 0;
+            for (int i = 0; i < P->sx; ++i) {
+                const __float128 bj = ((__float128)j + 0.5Q) * P->dy, ai = ((__float128)i + 0.5Q) * P->dx;
+                const __float128 x0 = (__float128)(p - P->pxl) * P->dx, y0 = (__float128)(q - P->pyl) * P->dy;
+                __float128 b[6];
+                b[0] = x0 - ai;
+                b[1] = x0 + P->dx - ai;
+                b[2] = y0 - bj;
+                b[3] = y0 + P->dy - bj;
+                b[4] = (__float128)P->zedge[r] + P->h;
+                b[5] = (__float128)P->zedge[r + 1] + P->h;
+                rowsum += (__float128)P->scale * orc_prism_q(P->kind, b, g, NULL) *
+                          (__float128)v[(int64_t)j * P->sx + i];
+            }
+            part[j] = rowsum;
+        }
+        __float128 acc = 0;
+        for (int j = 0; j < P->sy; ++j) acc += part[j];
+        out[s] = (double)acc;
+    }
+    free(part);
+    return 0;
+}

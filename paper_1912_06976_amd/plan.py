@@ -31,6 +31,10 @@ def _stream_ptr(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(int(stream.cuda_stream))
 
 
+def _stream_obj(stream):
+    return torch.cuda.current_stream() if stream is None else stream
+
+
 def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
     return ctypes.c_void_p(int(t.data_ptr()))
 
@@ -176,7 +180,10 @@ class Plan:
 
     ``Plan(problem, precision)`` validates the problem (host only);
     ``generate()`` allocates the spectra and fills them on the GPU;
-    ``forward(m)`` / ``transpose(r)`` run the products on torch's current stream.
+    ``forward(m)`` / ``transpose(r)`` run the products on torch's current stream
+    (or the ``stream`` argument).  Each stream gets its own cached workspace,
+    allocated on that stream, and default outputs are allocated on the stream
+    the product runs on, so products of one plan may run on several streams.
     """
 
     def __init__(self, problem: dict, precision: str = "fp32", accumulation: str = "default",
@@ -192,7 +199,7 @@ class Plan:
         self.nx = self.sx + problem.get("pxl", 0) + problem.get("pxr", 0)
         self.ny = self.sy + problem.get("pyl", 0) + problem.get("pyr", 0)
         self.spectra = None
-        self._ws = None
+        self._ws = {}          # cached workspace per stream (keyed by the HIP stream handle)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -207,12 +214,21 @@ class Plan:
     def workspace_bytes(self, nrhs: int = 1) -> int:
         return bttb_plan_query(self.handle, nrhs)[1]
 
-    def workspace(self, nrhs: int = 1) -> torch.Tensor:
+    def workspace(self, nrhs: int = 1, stream=None) -> torch.Tensor:
+        """The workspace of products with nrhs right-hand sides on `stream`
+        (default: the current stream), cached per stream and allocated on it:
+        a larger replacement frees the old block on the same stream, after
+        the products already queued there."""
+        s = _stream_obj(stream)
+        key = int(s.cuda_stream)
         need = self.workspace_bytes(nrhs)
-        if self._ws is None or self._ws.numel() < need:
-            self._ws = None
-            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
-        return self._ws
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < need:
+            self._ws.pop(key, None)
+            with torch.cuda.stream(s):
+                ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        return ws
 
     # -- operations ---------------------------------------------------------
     def generate(self, table: torch.Tensor | None = None, stream=None) -> "Plan":
@@ -227,9 +243,10 @@ class Plan:
             want = (self.nz, self.sy + self.ny - 1, self.sx + self.nx - 1)
             if tuple(table.shape) != want:
                 raise ValueError("table has shape %s, expected %s" % (tuple(table.shape), want))
-            bttb_kernel_generate_table(self.handle, table.contiguous(), self.spectra, self.workspace(1), stream)
+            bttb_kernel_generate_table(self.handle, table.contiguous(), self.spectra, self.workspace(1, stream),
+                                       stream)
         else:
-            bttb_kernel_generate(self.handle, self.spectra, self.workspace(1), stream)
+            bttb_kernel_generate(self.handle, self.spectra, self.workspace(1, stream), stream)
         return self
 
     def _check_vec(self, t: torch.Tensor, tail, name):
@@ -244,12 +261,13 @@ class Plan:
             raise RuntimeError("call generate() first")
         nrhs = self._check_vec(m, (self.nz, self.ny, self.nx), "m")
         if out is None:
-            out = torch.empty(m.shape[:-3] + (self.sy, self.sx), dtype=self.dtype, device=m.device)
+            with torch.cuda.stream(_stream_obj(stream)):
+                out = torch.empty(m.shape[:-3] + (self.sy, self.sx), dtype=self.dtype, device=m.device)
         if self._check_vec(out, (self.sy, self.sx), "out") != nrhs:
             raise ValueError("out holds a different number of right-hand sides than m")
         if nrhs == 0:
             return out
-        bttb_forward(self.handle, self.spectra, m, out, nrhs, self.workspace(nrhs), stream)
+        bttb_forward(self.handle, self.spectra, m, out, nrhs, self.workspace(nrhs, stream), stream)
         return out
 
     def transpose(self, r: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
@@ -257,12 +275,13 @@ class Plan:
             raise RuntimeError("call generate() first")
         nrhs = self._check_vec(r, (self.sy, self.sx), "r")
         if out is None:
-            out = torch.empty(r.shape[:-2] + (self.nz, self.ny, self.nx), dtype=self.dtype, device=r.device)
+            with torch.cuda.stream(_stream_obj(stream)):
+                out = torch.empty(r.shape[:-2] + (self.nz, self.ny, self.nx), dtype=self.dtype, device=r.device)
         if self._check_vec(out, (self.nz, self.ny, self.nx), "out") != nrhs:
             raise ValueError("out holds a different number of right-hand sides than r")
         if nrhs == 0:
             return out
-        bttb_transpose(self.handle, self.spectra, r, out, nrhs, self.workspace(nrhs), stream)
+        bttb_transpose(self.handle, self.spectra, r, out, nrhs, self.workspace(nrhs, stream), stream)
         return out
 
     def cgls(self, d: torch.Tensor, lam: float, iterations: int, m0: torch.Tensor | None = None, stream=None):
@@ -275,18 +294,20 @@ class Plan:
         self._check_vec(d, (self.sy, self.sx), "d")
         if d.dim() != 2:
             raise ValueError("d must be [sy, sx] (one right-hand side)")
-        if m0 is None:
-            m = torch.zeros((self.nz, self.ny, self.nx), dtype=self.dtype, device=d.device)
-        else:
+        if m0 is not None:
             self._check_vec(m0, (self.nz, self.ny, self.nx), "m0")
-            m = m0.clone()
-        hist = torch.zeros((iterations + 1, 3), dtype=torch.float64, device=d.device)
-        ws = torch.empty(bttb_cgls_query(self.handle), dtype=torch.uint8, device=d.device)
+        with torch.cuda.stream(_stream_obj(stream)):
+            if m0 is None:
+                m = torch.zeros((self.nz, self.ny, self.nx), dtype=self.dtype, device=d.device)
+            else:
+                m = m0.clone()
+            hist = torch.zeros((iterations + 1, 3), dtype=torch.float64, device=d.device)
+            ws = torch.empty(bttb_cgls_query(self.handle), dtype=torch.uint8, device=d.device)
         bttb_cgls(self.handle, self.spectra, d, m, lam, iterations, hist, ws, stream)
         return m, hist
 
     def debug_generator(self, layer: int) -> np.ndarray:
-        return bttb_debug_generator(self.handle, layer, self.workspace(1))
+        return bttb_debug_generator(self.handle, layer, self.workspace(1), None)
 
 
 def bttb_batch_create(plans, max_nrhs: int = 1) -> int:

@@ -59,6 +59,42 @@ def test_batch48_equals_single_calls_and_replays(torch_cuda):
         assert torch.equal(extra, ref_d[rep])
 
 
+def test_batch48_against_oracle_samples(torch_cuda):
+    # every instance of the 48-instance batch (its own transform lengths and
+    # spectrum forms, 4 right-hand sides) against the oracle's direct sums at
+    # seeded stations and prisms: rows of G m for right-hand sides 0 and 3,
+    # columns of G^T r for right-hand sides 1 and 2 (FP32 bar 2e-5, rel-L2
+    # over the sample)
+    torch = torch_cuda
+    import oracle
+    from paper_1912_06976_amd import Batch, Plan
+    probs = W.batch48()
+    plans = [Plan(p, "fp32").generate() for p in probs]
+    ms, rs = _inputs(torch, plans, 4, 401)
+    batch = Batch(plans, max_nrhs=4)
+    ds, mts = batch.run(ms, rs)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for k, pr in enumerate(probs):
+        P = oracle_problem(pr)
+        st, pq = W.fullsize_samples(pr, 3, 4, seed=6000 + 10 * k)
+        got, ref = [], []
+        for q in (0, 3):
+            d = ds[k][q].double().cpu().numpy()
+            ref += list(oracle.station_sums(P, ms[k][q].double().cpu().numpy(), st))
+            got += [d[j, i] for (i, j) in st]
+        err_f = rel_l2(np.array(got), np.array(ref))
+        got, ref = [], []
+        for q in (1, 2):
+            t = mts[k][q].double().cpu().numpy()
+            ref += list(oracle.prism_sums(P, rs[k][q].double().cpu().numpy(), pq))
+            got += [t[r, qq, p] for (p, qq, r) in pq]
+        err_t = rel_l2(np.array(got), np.array(ref))
+        worst = max(worst, err_f, err_t)
+        assert err_f <= 2e-5 and err_t <= 2e-5, (k, plans[k].nx_fft, plans[k].ny_fft, err_f, err_t)
+    print("batch48 worst sampled rel-L2 against the oracle: %.2e" % worst, flush=True)
+
+
 def test_batch_partial_products_and_rhs_counts(torch_cuda):
     torch = torch_cuda
     from paper_1912_06976_amd import Batch, Plan

@@ -486,3 +486,65 @@ def test_dense_from_table_reproduces_geometry_entries(oracle_lib, pr):
     P = oracle.problem_from_dict(pr)
     t, _ = oracle.offset_table_quad(P)
     assert np.array_equal(oracle.dense_from_table(pr, t), oracle.dense_G_quad(P))
+
+
+# ----------------------------------------------------------------------------
+# station height
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("h", [7.5, 40.0])
+def test_station_height_entries_match_quadrature(oracle_lib, h):
+    # A raised station at c = -h sees the prism's depth range [z_r, z_{r+1}]
+    # at vertical distances [z_r + h, z_{r+1} + h].  The box is built here
+    # from the station and prism coordinates (Table 3) and the integrand is
+    # integrated by quadrature; the oracle's entries (through the problem's
+    # station height, in double and in quad, and its dense matrix) must agree.
+    # A slip in the sign or placement of h moves the box and fails this.
+    import oracle
+    for kind, kw in ((oracle.GRAVITY, {}), (oracle.MAGNETIC, dict(incl=50.0, decl=-25.0))):
+        P = oracle.Problem(kind=kind, sx=5, sy=4, nz=3, pxl=1, pxr=2, pyl=2, pyr=0, dx=40.0, dy=30.0,
+                           z_edges=np.array([0.0, 10.0, 35.0, 50.0]), h=h, scale=1.0, **kw)
+        G = oracle_lib.dense_G(P)
+        z = P.zedges()
+        for (i, j, p, q, r) in [(0, 0, 1, 2, 0), (3, 2, 0, 5, 1), (4, 3, 7, 1, 2), (2, 1, 3, 3, 0)]:
+            a, b = (i + 0.5) * P.dx, (j + 0.5) * P.dy
+            box = ((p - P.pxl) * P.dx - a, (p - P.pxl + 1) * P.dx - a,
+                   (q - P.pyl) * P.dy - b, (q - P.pyl + 1) * P.dy - b,
+                   z[r] - (-h), z[r + 1] - (-h))
+            fun = gz_integrand if kind == oracle.GRAVITY else tmi_integrand(field_dir(P.incl, P.decl))
+            ref = gauss_legendre_box(fun, box, n=24, sub=4)
+            vq, _ = oracle_lib.entry(P, i, j, p, q, r, quad=True)
+            vd, _ = oracle_lib.entry(P, i, j, p, q, r, quad=False)
+            gd = G[j * P.sx + i, r * P.nx * P.ny + q * P.nx + p]
+            for v in (vq, vd, gd):
+                assert abs(v - ref) <= 1e-10 * abs(ref), (kind, i, j, p, q, r, v, ref)
+        # and a station height of 0 gives a different entry (h is used)
+        P0 = oracle.Problem(**{**P.__dict__, "h": 0.0, "_keep": []})
+        assert abs(oracle_lib.entry(P0, 0, 0, 1, 2, 0)[0] - oracle_lib.entry(P, 0, 0, 1, 2, 0)[0]) > 1e-3 * abs(
+            oracle_lib.entry(P, 0, 0, 1, 2, 0)[0])
+
+
+def test_quad_direct_sums_match_dense_quad_matrix(oracle_lib):
+    # the __float128 row and column sums against the dense matrix of quad
+    # entries (summed exactly here with math.fsum)
+    import math as _m
+    import oracle
+    for pr in (W.problem(W.MAGNETIC, 9, 7, 3, 2, 1, 1, 2, dx=50.0, dy=50.0, dz=25.0, incl=60.0, decl=15.0,
+                         field_nT=47000.0, h=5.0),
+               W.problem(W.GRAVITY, 8, 6, 4, 1, 2, 2, 0, dx=25.0, dy=25.0, dz=20.0, h=2.0)):
+        P = oracle.problem_from_dict(pr)
+        Gq = oracle_lib.dense_G_quad(P)
+        m = W.normal_model(pr, 17).ravel()
+        v = W.normal_data(pr, 18).ravel()
+        st = [(0, 0), (P.sx - 1, P.sy - 1), (3, 2)]
+        pq = [(0, 0, 0), (P.nx - 1, P.ny - 1, P.nz - 1), (4, 3, 1)]
+        ds = oracle_lib.station_sums(P, m, st, quad=True)
+        ts = oracle_lib.prism_sums(P, v, pq, quad=True)
+        for (i, j), val in zip(st, ds):
+            row = Gq[j * P.sx + i]
+            ref = _m.fsum(row * m)
+            assert abs(val - ref) <= 1e-14 * (np.abs(row) @ np.abs(m))
+        for (p, q, r), val in zip(pq, ts):
+            col = Gq[:, r * P.nx * P.ny + q * P.nx + p]
+            ref = _m.fsum(col * v)
+            assert abs(val - ref) <= 1e-14 * (np.abs(col) @ np.abs(v))

@@ -178,3 +178,32 @@ def sample_indices(seed, count, upper):
     """``count`` distinct seeded indices in [0, upper)."""
     rng = np.random.default_rng(seed)
     return np.sort(rng.choice(upper, size=min(count, upper), replace=False))
+
+
+def fullsize_samples(pr, nst, npr, seed=910):
+    """Seeded sample of stations (i, j) and prisms (p, q, r) of a large
+    problem: the corners of the station grid and of the volume, plus ``nst``
+    stations and ``npr`` prisms drawn without replacement per axis."""
+    nx, ny, nz = dims(pr)
+    st = [(0, 0), (pr["sx"] - 1, pr["sy"] - 1)] + list(zip(sample_indices(seed, nst, pr["sx"]).tolist(),
+                                                         sample_indices(seed + 1, nst, pr["sy"]).tolist()))
+    pq = [(0, 0, 0), (nx - 1, ny - 1, nz - 1)] + list(zip(sample_indices(seed + 2, npr, nx).tolist(),
+                                                        sample_indices(seed + 3, npr, ny).tolist(),
+                                                        np.random.default_rng(seed + 4).integers(0, nz, npr).tolist()))
+    return st, pq
+
+
+def fullsize_case(name):
+    """The large problems with their seeded inputs and sample sizes:
+    (problem, m, r, stations, prisms)."""
+    if name == "gravity_1024":
+        pr = gravity_1024()
+        m, r = ellipsoid_model(pr, 301), normal_data(pr, 302)
+        st, pq = fullsize_samples(pr, 8, 32)
+    elif name == "magnetic_288":
+        pr = magnetic_288()
+        m, r = box_model(pr, 501, nboxes=5), normal_data(pr, 502)
+        st, pq = fullsize_samples(pr, 16, 48)
+    else:
+        raise KeyError(name)
+    return pr, m, r, st, pq
