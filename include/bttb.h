@@ -205,6 +205,31 @@ bttb_status bttb_forward(bttb_plan_t plan, const void* spectra, const void* m, v
 bttb_status bttb_transpose(bttb_plan_t plan, const void* spectra, const void* r, void* mt,
                            int32_t nrhs, void* workspace, size_t ws_bytes, void* stream);
 
+/* Bytes of the library's own device scratch array used by
+ * bttb_forward_noalloc (64 MiB; one copy per GPU the library runs on, held
+ * until the process ends). */
+#define BTTB_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* d = G m exactly as bttb_forward, without a workspace argument: for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  The workspace bttb_forward
+ * would take lives in a file-scope device array of BTTB_NOALLOC_SCRATCH_BYTES
+ * inside the library; the call allocates nothing (no hipMalloc, no hipFree,
+ * no allocating library routine).  Results equal bttb_forward's bit for bit
+ * for the same plan, spectra, m and nrhs.
+ * The stream (NULL = default stream) must belong to the current device; the
+ * first call on a device looks up that device's copy of the array.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (other streams, other threads, other plans) race and must be
+ * ordered by the caller.  The array keeps the last call's contents; nothing
+ * in it needs to start at zero.
+ * Errors: as bttb_forward, plus UNSUPPORTED when the workspace of the plan
+ * for nrhs right-hand sides (bttb_plan_query) exceeds
+ * BTTB_NOALLOC_SCRATCH_BYTES, INVALID_VALUE when the stream belongs to
+ * another device, HIP when the array's address cannot be obtained. */
+bttb_status bttb_forward_noalloc(bttb_plan_t plan, const void* spectra, const void* m, void* d,
+                                 int32_t nrhs, void* stream);
+
 /* ------------------------------------------------------------------------
  * Inversion driver: the regularised least-squares problem
  *     min_m ||G m - d||^2 + lambda^2 ||m||^2

@@ -16,11 +16,13 @@ BTTB_GRAVITY_GZ, BTTB_MAGNETIC_TMI, BTTB_USER_TABLE, BTTB_PROBE = 0, 1, 2, 99
 BTTB_FP32, BTTB_FP64 = 0, 1
 BTTB_ACC_DEFAULT, BTTB_ACC_PLAIN, BTTB_ACC_TWOSUM, BTTB_ACC_WIDE = 0, 1, 2, 3
 BTTB_SPECTRUM_AUTO, BTTB_SPECTRUM_COMPLEX, BTTB_SPECTRUM_REAL_EVEN = 0, 1, 2
+#: BTTB_NOALLOC_SCRATCH_BYTES: the device scratch array of bttb_forward_noalloc
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 #: every symbol include/bttb.h declares
 EXPORTS = ["bttb_plan_create", "bttb_plan_destroy", "bttb_plan_query", "bttb_kernel_generate",
-           "bttb_forward", "bttb_transpose", "bttb_forward_profiled", "bttb_transpose_profiled",
-           "bttb_debug_generator", "bttb_plan_spectrum_form", "bttb_kernel_generate_table", "bttb_cgls_query", "bttb_cgls", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
+           "bttb_forward", "bttb_transpose", "bttb_forward_noalloc", "bttb_forward_profiled",
+           "bttb_transpose_profiled", "bttb_debug_generator", "bttb_plan_spectrum_form", "bttb_kernel_generate_table", "bttb_cgls_query", "bttb_cgls", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
            "bttb_batch_destroy", "bttb_autotune_query", "bttb_autotune", "bttb_status_string",
            "bttb_last_error"]
 
@@ -74,6 +76,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     L.bttb_kernel_generate.argtypes = [vp, vp, vp, sz, vp]
     L.bttb_forward.argtypes = [vp, vp, vp, vp, i32, vp, sz, vp]
     L.bttb_transpose.argtypes = [vp, vp, vp, vp, i32, vp, sz, vp]
+    L.bttb_forward_noalloc.argtypes = [vp, vp, vp, vp, i32, vp]
     L.bttb_forward_profiled.argtypes = [vp, vp, vp, vp, i32, vp, sz, vp, ctypes.POINTER(ctypes.c_float)]
     L.bttb_transpose_profiled.argtypes = [vp, vp, vp, vp, i32, vp, sz, vp, ctypes.POINTER(ctypes.c_float)]
     L.bttb_debug_generator.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), vp, sz, vp]
@@ -93,8 +96,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
     L.bttb_last_error.argtypes = []
     L.bttb_last_error.restype = ctypes.c_char_p
     for name in ["bttb_plan_create", "bttb_plan_destroy", "bttb_plan_query", "bttb_kernel_generate",
-                 "bttb_forward", "bttb_transpose", "bttb_forward_profiled", "bttb_transpose_profiled",
-                 "bttb_debug_generator", "bttb_plan_spectrum_form", "bttb_kernel_generate_table", "bttb_cgls_query", "bttb_cgls", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
+                 "bttb_forward", "bttb_transpose", "bttb_forward_noalloc", "bttb_forward_profiled",
+                 "bttb_transpose_profiled", "bttb_debug_generator", "bttb_plan_spectrum_form", "bttb_kernel_generate_table", "bttb_cgls_query", "bttb_cgls", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
                  "bttb_batch_destroy", "bttb_autotune_query", "bttb_autotune"]:
         getattr(L, name).restype = ctypes.c_int
     _handle = L

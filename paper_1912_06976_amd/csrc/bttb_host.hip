@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -704,6 +705,48 @@ bttb_status run_cgls(const bttb_plan_s* P, const char* spec, const T* d, T* m, d
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// forward product without a workspace argument
+// ---------------------------------------------------------------------------
+// The forward product's workspace (row transforms X, column results Y, the
+// depth split's partial sums) for callers that cannot allocate: a file-scope
+// device array, one copy per GPU.  Its host-side name is only a stand-in:
+// host code takes each device's address from hipGetSymbolAddress (looked up
+// once per device, with that device current) and passes that pointer to the
+// kernels like any workspace.  No kernel of the forward product needs any
+// part of it to start at zero (each reads only what the same call wrote).
+static __device__ __align__(256) unsigned char scratch[BTTB_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the current device's copy of `scratch`; the stream must belong to it
+bttb_status scratch_for(hipStream_t s, void** out)
+{
+    int dev = -1;
+    bttb_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (st != BTTB_OK) return st;
+    if (dev < 0 || dev >= kMaxDevices) return fail(BTTB_ERR_UNSUPPORTED, "device index above 63");
+    if (s) {
+        int sdev = -1;
+        if ((st = hip_check(hipStreamGetDevice(s, &sdev), "hipStreamGetDevice")) != BTTB_OK) return st;
+        if (sdev != dev) return fail(BTTB_ERR_INVALID_VALUE, "the stream belongs to another device than the current one");
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if ((st = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)")) != BTTB_OK)
+            return st;
+        if (!p) return fail(BTTB_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return BTTB_OK;
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // extern "C" entry points
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -850,6 +893,33 @@ bttb_status bttb_transpose(bttb_plan_t plan, const void* spectra, const void* r,
                           : run_single<float>(false, plan, (const char*)spectra, r, mt, nrhs, (char*)workspace, s);
     } catch (...) {
         return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_transpose");
+    }
+}
+
+bttb_status bttb_forward_noalloc(bttb_plan_t plan, const void* spectra, const void* m, void* d, int32_t nrhs,
+                                 void* stream)
+{
+    try {
+        g_last_error.clear();
+        if (!plan) return fail(BTTB_ERR_NULL_POINTER, "plan must not be NULL");
+        if (nrhs < 1) return fail(BTTB_ERR_INVALID_VALUE, "nrhs must be >= 1");
+        const size_t need = ws_layout(plan, nrhs).total;
+        if (need > BTTB_NOALLOC_SCRATCH_BYTES)
+            return fail(BTTB_ERR_UNSUPPORTED,
+                        "the forward product needs " + std::to_string(need) +
+                            " bytes of workspace; bttb_forward_noalloc holds at most " +
+                            std::to_string((size_t)BTTB_NOALLOC_SCRATCH_BYTES) +
+                            " (use bttb_forward with a caller workspace, or fewer right-hand sides)");
+        hipStream_t s = (hipStream_t)stream;
+        void* ws = nullptr;
+        bttb_status st = scratch_for(s, &ws);
+        if (st != BTTB_OK) return st;
+        st = check_product(true, plan, spectra, m, d, nrhs, ws, BTTB_NOALLOC_SCRATCH_BYTES);
+        if (st != BTTB_OK) return st;
+        return plan->fp64 ? run_single<double>(true, plan, (const char*)spectra, m, d, nrhs, (char*)ws, s)
+                          : run_single<float>(true, plan, (const char*)spectra, m, d, nrhs, (char*)ws, s);
+    } catch (...) {
+        return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_forward_noalloc");
     }
 }
 

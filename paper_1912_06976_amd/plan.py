@@ -120,6 +120,15 @@ def bttb_forward(plan: int, spectra: torch.Tensor, m: torch.Tensor, d: torch.Ten
                                    _stream_ptr(stream)))
 
 
+def bttb_forward_noalloc(plan: int, spectra: torch.Tensor, m: torch.Tensor, d: torch.Tensor, nrhs: int,
+                         stream=None) -> None:
+    """bttb_forward with the library's own device scratch array as workspace
+    (no allocation; calls on one GPU must not overlap)."""
+    check("bttb_forward_noalloc",
+          _lib.load().bttb_forward_noalloc(ctypes.c_void_p(plan), _ptr(spectra), _ptr(m), _ptr(d), nrhs,
+                                           _stream_ptr(stream)))
+
+
 def bttb_transpose(plan: int, spectra: torch.Tensor, r: torch.Tensor, mt: torch.Tensor, nrhs: int,
                    workspace: torch.Tensor, stream=None) -> None:
     check("bttb_transpose",

@@ -223,3 +223,30 @@ def test_autotune_query_size(lib):
     vec = 2 * (1024 * 1024 * 128 + 1000 * 1000) * 4
     assert sb + wb + vec <= sz.value <= sb + wb + vec + 8 * 256
     assert lib.bttb_autotune_query(ctypes.byref(d), 0, ctypes.byref(sz)) == 1
+
+
+def test_noalloc_forward_argument_checks(lib):
+    # fake (never dereferenced) device pointers: every check here fails
+    # before the library touches the device
+    import paper_1912_06976_amd as B
+    from paper_1912_06976_amd import _lib
+    P = ctypes.c_void_p
+    p = P(1 << 20)
+    assert lib.bttb_forward_noalloc(None, p, p, p, 1, None) == 2
+    h = B.bttb_plan_create(W.small_gravity(), "fp32")
+    assert lib.bttb_forward_noalloc(P(h), p, p, p, 0, None) == 1
+    B.bttb_plan_destroy(h)
+    # a workspace above the scratch array's size is refused, with the sizes
+    h = B.bttb_plan_create(W.gravity_1024(), "fp32")
+    assert B.bttb_plan_query(h, 1)[1] > _lib.NOALLOC_SCRATCH_BYTES
+    assert lib.bttb_forward_noalloc(P(h), p, p, p, 1, None) == 3
+    msg = lib.bttb_last_error().decode()
+    assert "bttb_forward_noalloc" in msg and str(_lib.NOALLOC_SCRATCH_BYTES) in msg
+    B.bttb_plan_destroy(h)
+
+
+def test_noalloc_scratch_size_matches_header():
+    txt = open(os.path.join(ROOT, "include", "bttb.h")).read()
+    from paper_1912_06976_amd import _lib
+    m = re.search(r"#define BTTB_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", txt)
+    assert m and int(m.group(1)) << int(m.group(2)) == _lib.NOALLOC_SCRATCH_BYTES
