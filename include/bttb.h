@@ -118,8 +118,15 @@ typedef struct {
     double field_nT;           /* field intensity F [nT], > 0 for BTTB_MAGNETIC_TMI    */
     double scale;              /* 0: default (6.6743e-3 mGal per (g/cm^3 m) for gravity,
                                   F / (4 pi) for the magnetic kernel, 1 for the probe) */
-    int32_t nx_fft, ny_fft;    /* 0: smallest power of two >= max(8, s + n - 1); else a
-                                  power of two in [max(8, s + n - 1), 4096]            */
+    int32_t nx_fft, ny_fft;    /* 0: the smallest supported length >= max(8, s + n - 1)
+                                  (the real even form, that is the gravity kernel
+                                  with spectrum_form AUTO or spectrum_form
+                                  REAL_EVEN: the smallest that also admits it);
+                                  else a supported length >= max(8, s + n - 1).
+                                  Supported: powers of two in [8, 4096] and
+                                  2^a 3^b with b = 1 or 2 in [96, 3072]
+                                  (96, 144, 192, 288, 384, 576, 768, 1152, 1536,
+                                  2304, 3072)                                          */
     int32_t accumulation;      /* bttb_accumulation                                    */
     int32_t layer_chunk;       /* tuning: layers per pass of the transpose product (0: all
                                   layers); smaller chunks keep the per-layer intermediate
@@ -311,9 +318,15 @@ bttb_status bttb_batch_destroy(bttb_batch_t batch);
 /* ------------------------------------------------------------------------
  * Autotuner (the analogue of FFTW's planner "wisdom" the paper's MATLAB
  * runs preload, Sec. 5): for one descriptor and right-hand-side count, time
- * the products on the device for every candidate kernel configuration
- * (row_tile in {2, 4, 8}, col_tile in {1, 2}, layer_chunk in {0, 8, 16, 32}
- * below nz) and return the descriptor with the fastest one filled in.
+ * the products on the device for every candidate configuration -- the FFT
+ * lengths along each axis whose nx_fft / ny_fft is 0 (the plan's default,
+ * the smallest supported length and the smallest power of two holding the
+ * circulant; the spectra are generated for each), and for each length pair
+ * row_tile in {2, 4, 8} (wavefronts per block of the row transforms),
+ * col_tile in {1, 2} and layer_chunk in {0, 8, 16, 32} below nz -- and
+ * return the descriptor with the fastest one filled in (nx_fft, ny_fft,
+ * row_tile, col_tile, layer_chunk).  The lengths change the products only by
+ * rounding.
  * Results are cached in a text file (path: environment variable
  * BTTB_TUNE_CACHE, default $HOME/.cache/bttb_autotune.txt), keyed by the
  * shape, precision, accumulation, nrhs and device; a cached key is returned

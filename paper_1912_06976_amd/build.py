@@ -2,7 +2,8 @@
 
     python -m paper_1912_06976_amd.build
 
-Compiles every HIP source under csrc/ for gfx950 and links them into
+Compiles every HIP translation unit under csrc/ for gfx950 (in parallel,
+longest first) and links them into
 paper_1912_06976_amd/libbttb.so.  Packed FP32 instructions are disabled
 (-packed-fp32-ops): the compiler must emit scalar-lane FP32 arithmetic only.
 """
@@ -18,7 +19,14 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.environ.get("BTTB_LIB_OUT", os.path.join(HERE, "libbttb.so"))
 BUILD = os.environ.get("BTTB_BUILD_DIR", os.path.join(ROOT, "_build"))
-SOURCES = ["bttb_kernels.hip", "bttb_cols.hip", "bttb_cgls.hip", "bttb_host.hip"]
+# kernels and their dispatch; the row and column kernels are instantiated per
+# group of transform lengths (bttb_rows_*.hip, bttb_cols_*.hip) so that the
+# translation units compile in parallel
+KERNEL_SOURCES = ["bttb_cols_d.hip", "bttb_rows_d.hip", "bttb_cols_c.hip", "bttb_rows_c.hip",
+                  "bttb_cols_b.hip", "bttb_rows_b.hip", "bttb_cols_a.hip", "bttb_rows_a.hip",
+                  "bttb_kernels.hip", "bttb_cols.hip"]
+SOURCES = KERNEL_SOURCES + ["bttb_cgls.hip", "bttb_host.hip"]
+JOBS = int(os.environ.get("BTTB_BUILD_JOBS", str(min(len(SOURCES), os.cpu_count() or 4))))
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("BTTB_ARCH", "gfx950")
@@ -41,7 +49,7 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     """Compile all sources (always) and link libbttb.so; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=max(1, JOBS)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs]

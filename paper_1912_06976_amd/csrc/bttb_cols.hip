@@ -1,612 +1,47 @@
-// bttb_cols.hip -- gfx950 column kernels of the two products: the y
-// transforms with the multiply-accumulate over depth layers in the Fourier
-// domain (Sec. 3, eq. GrviaT summed over layers; Sec. 5, eq. Gslice).
-//
-//   k_cols_fwd_mac   forward product: per column kx, the depth loop
-//                    A += T^_r * FFT_y(X_r) with an extended accumulator, then
-//                    one inverse FFT_y (or, with the layers split into ranges,
-//                    the range's FP64 sum)
-//   k_cols_fwd_fin   adds the ranges' sums in order and finishes the column
-//   k_cols_tr_mac    transpose product: R^ = FFT_y(R) once per column, then per
-//                    layer IFFT_y(conj(T^_r) R^)
-//
-// Both kernels read the stored spectra in one of two forms (template
-// parameter SF):
-//   FORM_COMPLEX    T^_r as packed complex half spectra, [r][kx][ky], N
-//                   complex values per column
-//   FORM_REAL_EVEN  for a generator that is even in both offsets and placed
-//                   centred on offset 0 (the symmetric gravity kernel), the
-//                   transform is real and even in kx and ky: only
-//                   R_r(kx, ky), kx in [0, Nx/2], ky in [0, Ny/2], is stored,
-//                   [r][kx][ky] with line stride `lds` (line Nx/2 holds
-//                   kx = Nx/2).  The product's generator is that one shifted
-//                   by (pxl, pyl) cells, whose transform is
-//                   T^(kx, ky) = P(kx, ky) R(kx, ky) with the phase
-//                   P = exp(2 pi i (pxl kx / Nx + pyl ky / Ny)); P does not
-//                   depend on the layer and is applied once per column:
-//                   after the depth sum (forward) or to R^ (transpose).
+// bttb_cols.hip -- dispatch of the column kernels of the two products
+// (cols_impl.h) on the transform length; the kernels of each length are
+// instantiated in bttb_cols_*.hip, one group of lengths per translation
+// unit so that they compile in parallel.
 #include "kern_common.h"
 
 namespace bttbk {
 
-// depth accumulators ------------------------------------------------------
-template <typename T, int ACC> struct Acc;
-template <typename T> struct Acc<T, ACC_PLAIN> {
-    cT<T> s;
-    __device__ __forceinline__ void zero() { s = mk<T>(0, 0); }
-    __device__ __forceinline__ void add(cT<T> p) { s.x += p.x; s.y += p.y; }
-    __device__ __forceinline__ cT<T> get() const { return s; }
-    __device__ __forceinline__ double2 wide() const { return make_double2(s.x, s.y); }
-};
-// compensated (TwoSum) accumulation in the working precision
-template <typename T> struct Acc<T, ACC_TWOSUM> {
-    cT<T> s, c;
-    __device__ __forceinline__ void zero() { s = mk<T>(0, 0); c = mk<T>(0, 0); }
-    __device__ __forceinline__ static void two_sum(T& s, T& c, T p) {
-        const T n = s + p;
-        const T bp = n - s;
-        const T e = (s - (n - bp)) + (p - bp);
-        s = n;
-        c += e;
-    }
-    __device__ __forceinline__ void add(cT<T> p) { two_sum(s.x, c.x, p.x); two_sum(s.y, c.y, p.y); }
-    __device__ __forceinline__ cT<T> get() const { return mk<T>(s.x + c.x, s.y + c.y); }
-    __device__ __forceinline__ double2 wide() const {
-        return make_double2((double)s.x + (double)c.x, (double)s.y + (double)c.y);
-    }
-};
-// FP64 accumulation of FP32 products
-template <typename T> struct Acc<T, ACC_WIDE> {
-    double sx, sy;
-    __device__ __forceinline__ void zero() { sx = 0.0; sy = 0.0; }
-    __device__ __forceinline__ void add(cT<T> p) { sx += (double)p.x; sy += (double)p.y; }
-    __device__ __forceinline__ cT<T> get() const { return mk<T>((T)sx, (T)sy); }
-    __device__ __forceinline__ double2 wide() const { return make_double2(sx, sy); }
-};
-
-// Column 0 of the packed format holds z = A + i B with A, B the transforms
-// of two real sequences (Hermitian).  With zr = z at -k:
-//   A = (z + conj zr) / 2,  B = (z - conj zr) / (2 i).
-template <typename T> __device__ __forceinline__ cT<T> herm_a(cT<T> z, cT<T> zr) {
-    return mk<T>((T)0.5 * (z.x + zr.x), (T)0.5 * (z.y - zr.y));
-}
-template <typename T> __device__ __forceinline__ cT<T> herm_b(cT<T> z, cT<T> zr) {
-    return mk<T>((T)0.5 * (z.y + zr.y), (T)0.5 * (zr.x - z.x));
-}
-
-// Store register lines (positions t + m TPL) into LDS line buffers so that
-// their values at the mirror positions -k can be read back one at a time.
-// Contain barriers: every thread of the block calls them; only `active`
-// threads write.
-template <typename T, int N>
-__device__ __forceinline__ void stage_line(const cT<T> (&u)[8], cT<T>* bu, int t, bool active)
-{
-    constexpr int TPL = N / 8;
-    __syncthreads();
-    if (active) {
-#pragma unroll
-        for (int m = 0; m < 8; ++m) bu[lpad(t + m * TPL)] = u[m];
-    }
-    __syncthreads();
-}
-template <typename T, int N>
-__device__ __forceinline__ void stage_pair(const cT<T> (&u)[8], const cT<T> (&w)[8], cT<T>* bu, cT<T>* bw,
-                                           int t, bool active)
-{
-    constexpr int TPL = N / 8;
-    __syncthreads();
-    if (active) {
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            bu[lpad(t + m * TPL)] = u[m];
-            bw[lpad(t + m * TPL)] = w[m];
-        }
-    }
-    __syncthreads();
-}
-template <int N> __device__ __forceinline__ int mirror_idx(int t, int m) {
-    return lpad((N - t - m * (N / 8)) & (N - 1));
-}
-
-// minimum waves per SIMD of the column kernels: FP64 keeps its twiddles (80
-// VGPRs) and the prefetch buffers in registers only with the full 512 VGPRs;
-// the FP32 transpose kernel fits three waves (168 VGPRs) without spills at
-// N = 2048 with one column per block (other shapes would spill)
-template <typename T> constexpr int col_waves() { return sizeof(T) == 8 ? 1 : BTTB_COL_WAVES; }
-template <typename T, int N, int CM> constexpr int col_waves_tr()
-{
-    return sizeof(T) == 8 ? 1 : (N == 2048 && CM == 1 ? 3 : BTTB_COL_WAVES);
-}
-
-// Real even form: position k = t + m TPL of a line reads the stored value at
-// min(k, N - k), i.e. t + m TPL for m < 4 and (8 - m) TPL - t for m >= 4
-// (m = 4, t = 0 is the Nyquist bin N/2).  Consecutive threads read
-// consecutive (or reversed consecutive) addresses.
-template <int N> __device__ __forceinline__ int fold_idx(int t, int m) {
-    return m < 4 ? t + m * (N / 8) : (8 - m) * (N / 8) - t;
-}
-
-// exp(2 pi i (a / Na + b / Nb)) for integers 0 <= a < Na, 0 <= b < Nb (powers
-// of two): the argument is exact in FP64
-template <typename T> __device__ __forceinline__ cT<T> phase(int a, int Na, int b, int Nb) {
-    double s, c;
-    sincospi(2.0 * ((double)a / (double)Na + (double)b / (double)Nb), &s, &c);
-    return mk<T>((T)c, (T)s);
-}
-
-// The real even form's stored values of layer r for one line of positions
-// t + m TPL: .x = R(kx, ky); for the packed column (kx = 0 and kx = Nx/2)
-// .y = (-1)^pxl R(Nx/2, ky), the x phase at Nx/2 folded in.
-template <typename T, int N>
-__device__ __forceinline__ void load_real_even(cT<T> (&tn)[8], const ColJob& J, int r, int col, bool packed, int t)
-{
-    const T* sp = (const T*)J.spec + ((int64_t)r * (J.ncols + 1) + col) * J.lds;
-#pragma unroll
-    for (int m = 0; m < 8; ++m) tn[m].x = sp[fold_idx<N>(t, m)];
-    if (packed) {
-        const T sgn = (J.px & 1) ? (T)-1 : (T)1;
-        const T* sq = (const T*)J.spec + ((int64_t)r * (J.ncols + 1) + J.ncols) * J.lds;
-#pragma unroll
-        for (int m = 0; m < 8; ++m) tn[m].y = sgn * sq[fold_idx<N>(t, m)];
-    } else {
-#pragma unroll
-        for (int m = 0; m < 8; ++m) tn[m].y = (T)0;
-    }
-}
-
-// End of the forward column pass for one line: the depth sum w of column
-// `col` (positions t + m TPL) times the phase of the real even form, the
-// inverse y transform, and the store of rows y < nb into block q of Y
-// (`store` false: transform only, every thread of the block takes part).
-template <typename T, int N, int SF>
-__device__ __forceinline__ void fwd_finish(cT<T> (&w)[8], const ColJob& J, int col, bool packed, bool store, int q,
-                                           cT<T>* xl, const LineTwiddles<T, N>& twl, int t)
-{
-    constexpr int TPL = N / 8;
-    if constexpr (SF == FORM_REAL_EVEN) {
-        // T^ = P R: the phase of this column (kx = 0 for the packed one)
-        const int ax = packed ? 0 : (int)(((int64_t)J.px * col) & (2 * J.ncols - 1));
-#pragma unroll
-        for (int m = 0; m < 8; ++m)
-            w[m] = cmul<T>(w[m], phase<T>(ax, 2 * J.ncols, (int)(((int64_t)J.py * (t + m * TPL)) & (N - 1)), N));
-    }
-    fft_line<T, N, +1, false>(w, xl, twl, t);
-    if (store) {
-        cT<T>* ys = (cT<T>*)J.b + (int64_t)q * J.ncols * J.ldb;
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const int y = t + m * TPL;
-            if (y < J.nb) ys[pidx(col, y, J.ncols)] = w[m];
-        }
-    }
-}
-
-// Forward column pass over every job of the table (one block per CPW
-// columns of one right-hand-side block and one layer range of one job).
-// Job: a = X, the packed row-pass output in panels, block (q, r) at
-// X + (q * nz + r) * ncols * lda, y < na = ny, nl = nz layers; b = Y, block
-// q at Y + q * ncols * ldb, y < nb = sy.  With ns = 1 a block sums all
-// layers and finishes the column; with ns > 1 the layers are split into ns
-// ranges and a block writes its range's sum, in FP64, to the partial sums p
-// (k_cols_fwd_fin adds them in range order and finishes).
-template <typename T, int N, int NR, int ACC, int CM, int SF>
-__global__ void __launch_bounds__((ColCfg<N, CM>::THREADS), (col_waves<T>()))
-k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
-{
-    using C = ColCfg<N, CM>;
-    constexpr int TPL = C::TPL;
-    constexpr int LL = lds_line_elems(N);
-    __shared__ cT<T> lds[(C::CPW + 1) * LL];
-    // XCD-ordered block index: neighbouring column blocks, whose panel
-    // segments share 128-byte lines, run on one XCD and share its L2
-    const int bid = xcd_order(blockIdx.x, gridDim.x);
-    const ColJob& J = jobs.j[find_job(jobs, bid)];
-    const cT<T>* __restrict__ X = (const cT<T>*)J.a;
-    const cT<T>* __restrict__ spec = (const cT<T>*)J.spec;
-    const int64_t ldx = J.lda;
-    const int ny = J.na, nz = J.nl, ncols = J.ncols, nrhs = J.nrhs;
-    // the right-hand-side blocks of one column block are consecutive blocks,
-    // which run at the same time on one XCD and share that column's spectra
-    // through its L2
-    const int nqb = (J.nrhs + NR - 1) / NR, ns = J.ns;
-    const int lb = bid - J.begin, rest = lb / nqb, split = rest % ns, cb = rest / ns;
-    const int cl = threadIdx.x / TPL, t = threadIdx.x % TPL;
-    const int col = cb * C::CPW + cl;
-    const int q0 = (lb % nqb) * NR;
-    const int rb = (int)((int64_t)split * nz / ns), re = (int)((int64_t)(split + 1) * nz / ns);
-    const bool ok = col < ncols;
-    const bool packed_blk = cb == 0;              // block holding column 0
-    const bool packed = packed_blk && cl == 0;
-    cT<T>* xl = lds + cl * LL;
-    cT<T>* xs2 = lds + C::CPW * LL;               // second buffer (column 0)
-    LineTwiddles<T, N> twl;
-    twl.load(tw, t);
-    Acc<T, ACC> acc[NR][8];
-#pragma unroll
-    for (int q = 0; q < NR; ++q)
-#pragma unroll
-        for (int m = 0; m < 8; ++m) acc[q][m].zero();
-    const bool zhi = ny <= N / 2;
-    const int ccol = ok ? col : 0;
-    // software pipeline: the next layer's spectra and input columns are
-    // loaded while the current layer is transformed
-    cT<T> tn[8], xn[NR][8];
-    auto load_layer = [&](int r) {
-        if constexpr (SF == FORM_COMPLEX) {
-            const cT<T>* sp = spec + ((int64_t)r * ncols + ccol) * N;
-#pragma unroll
-            for (int m = 0; m < 8; ++m) tn[m] = sp[t + m * TPL];
-        } else {
-            load_real_even<T, N>(tn, J, r, ccol, packed, t);
-        }
-#pragma unroll
-        for (int q = 0; q < NR; ++q) {
-            const int qq = q0 + q;
-            const cT<T>* xs = X + ((int64_t)(qq < nrhs ? qq : 0) * nz + r) * ncols * ldx;
-#pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                const int y = t + m * TPL;
-                xn[q][m] = (ok && qq < nrhs && y < ny) ? xs[pidx(ccol, y, ncols)] : mk<T>(0, 0);
-            }
-        }
-    };
-    constexpr bool PIPE = true;
-    if (PIPE) load_layer(rb);
-    for (int r = rb; r < re; ++r) {
-        if (!PIPE) load_layer(r);
-        cT<T> tv[8], v[NR][8];
-#pragma unroll
-        for (int m = 0; m < 8; ++m) tv[m] = tn[m];
-#pragma unroll
-        for (int q = 0; q < NR; ++q)
-#pragma unroll
-            for (int m = 0; m < 8; ++m) v[q][m] = xn[q][m];
-        if (PIPE && r + 1 < re) load_layer(r + 1);
-#pragma unroll
-        for (int q = 0; q < NR; ++q) {
-            if (zhi) fft_line<T, N, -1, true>(v[q], xl, twl, t);
-            else fft_line<T, N, -1, false>(v[q], xl, twl, t);
-            if constexpr (SF == FORM_COMPLEX) {
-                if (packed_blk) {
-                    stage_pair<T, N>(v[q], tv, xl, xs2, t, packed);
-                    if (packed) {
-                        // column 0 carries bins 0 and N/2: accumulate
-                        // T0 F0 + i T1 F1 of the separated Hermitian parts
-#pragma unroll
-                        for (int m = 0; m < 8; ++m) {
-                            const int mi = mirror_idx<N>(t, m);
-                            const cT<T> vr = xl[mi], tr = xs2[mi];
-                            const cT<T> p0 = cmul<T>(herm_a<T>(tv[m], tr), herm_a<T>(v[q][m], vr));
-                            const cT<T> p1 = cmul<T>(herm_b<T>(tv[m], tr), herm_b<T>(v[q][m], vr));
-                            acc[q][m].add(mk<T>(p0.x - p1.y, p0.y + p1.x));
-                        }
-                        continue;
-                    }
-                }
-#pragma unroll
-                for (int m = 0; m < 8; ++m) acc[q][m].add(cmul<T>(tv[m], v[q][m]));
-            } else {
-                if (packed_blk) {
-                    stage_line<T, N>(v[q], xl, t, packed);
-                    if (packed) {
-                        // R(0) F0 + i (-1)^pxl R(Nx/2) F1 (R is even: no mirror)
-#pragma unroll
-                        for (int m = 0; m < 8; ++m) {
-                            const cT<T> vr = xl[mirror_idx<N>(t, m)];
-                            const cT<T> a = herm_a<T>(v[q][m], vr), b = herm_b<T>(v[q][m], vr);
-                            acc[q][m].add(mk<T>(tv[m].x * a.x - tv[m].y * b.y, tv[m].x * a.y + tv[m].y * b.x));
-                        }
-                        continue;
-                    }
-                }
-#pragma unroll
-                for (int m = 0; m < 8; ++m) acc[q][m].add(mk<T>(tv[m].x * v[q][m].x, tv[m].x * v[q][m].y));
-            }
-        }
-    }
-    if (ns > 1) {
-        // this layer range's sum, for k_cols_fwd_fin (ns is uniform in the
-        // block: no thread is left at a barrier)
-#pragma unroll
-        for (int q = 0; q < NR; ++q) {
-            const int qq = q0 + q;
-            if (ok && qq < nrhs) {
-                double2* pp = (double2*)J.p + (((int64_t)qq * ns + split) * ncols + col) * N;
-#pragma unroll
-                for (int m = 0; m < 8; ++m) pp[t + m * TPL] = acc[q][m].wide();
-            }
-        }
-        return;
-    }
-#pragma unroll
-    for (int q = 0; q < NR; ++q) {
-        const int qq = q0 + q;
-        cT<T> w[8];
-#pragma unroll
-        for (int m = 0; m < 8; ++m) w[m] = acc[q][m].get();
-        fwd_finish<T, N, SF>(w, J, ccol, packed, ok && qq < nrhs, qq, xl, twl, t);
-    }
-}
-
-// Finishing kernel of the forward column pass for jobs with ns > 1: one
-// block per CPW columns of one right-hand side (block order as in
-// k_cols_fwd_mac), which adds the ns partial depth sums in range order in
-// FP64 and finishes the columns (phase, inverse y transform, store).
-template <typename T, int N, int CM, int SF>
-__global__ void __launch_bounds__((ColCfg<N, CM>::THREADS)) k_cols_fwd_fin(ColJobs jobs, const cT<T>* __restrict__ tw)
-{
-    using C = ColCfg<N, CM>;
-    constexpr int TPL = C::TPL;
-    constexpr int LL = lds_line_elems(N);
-    __shared__ cT<T> lds[C::CPW * LL];
-    const int bid = xcd_order(blockIdx.x, gridDim.x);
-    const ColJob& J = jobs.j[find_job(jobs, bid)];
-    const int lb = bid - J.begin, q = lb % J.nrhs, cb = lb / J.nrhs;
-    const int cl = threadIdx.x / TPL, t = threadIdx.x % TPL;
-    const int col = cb * C::CPW + cl, ns = J.ns;
-    const bool ok = col < J.ncols;
-    LineTwiddles<T, N> twl;
-    twl.load(tw, t);
-    double sx[8], sy[8];
-#pragma unroll
-    for (int m = 0; m < 8; ++m) sx[m] = sy[m] = 0.0;
-    if (ok) {
-        const double2* pp = (const double2*)J.p + ((int64_t)q * ns * J.ncols + col) * N;
-        for (int s = 0; s < ns; ++s, pp += (int64_t)J.ncols * N) {
-#pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                const double2 v = pp[t + m * TPL];
-                sx[m] += v.x;
-                sy[m] += v.y;
-            }
-        }
-    }
-    cT<T> w[8];
-#pragma unroll
-    for (int m = 0; m < 8; ++m) w[m] = mk<T>((T)sx[m], (T)sy[m]);
-    fwd_finish<T, N, SF>(w, J, ok ? col : 0, cb == 0 && cl == 0, ok, q, lds + cl * LL, twl, t);
-}
-
-// Transpose column pass over every job of the table, layers [r0, r0 + nl).
-// Job: a = R, the packed row-pass output of the data in panels, block q at
-// R + q * ncols * lda, y < na = sy; b = Z, block (q, r - r0) at
-// Z + (q * nl + r - r0) * ncols * ldb, y < nb = ny.
-// The kernel is persistent and balanced: the work of all jobs is the list of
-// units (job, column block cb, right-hand side q, layer l), layer fastest,
-// and block w processes the contiguous range [w U / G, (w + 1) U / G).  The
-// right-hand sides of one column block thus fall to neighbouring blocks,
-// which run at the same time on one XCD and share its spectra through L2.  A
-// block recomputes R^ = FFT_y(R) whenever its range enters a new column
-// block (at most a few times), so every block gets the same number of layers
-// whatever the number of resident blocks.
-template <typename T, int N, int NR, int CM, int SF>
-__global__ void __launch_bounds__((ColCfg<N, CM>::THREADS), (col_waves_tr<T, N, CM>()))
-k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
-{
-    using C = ColCfg<N, CM>;
-    constexpr int TPL = C::TPL;
-    constexpr int LL = lds_line_elems(N);
-    __shared__ cT<T> lds[(C::CPW + 1) * LL];
-    const int cl = threadIdx.x / TPL, t = threadIdx.x % TPL;
-    cT<T>* xl = lds + cl * LL;
-    cT<T>* xs2 = lds + C::CPW * LL;
-    LineTwiddles<T, N> twl;
-    twl.load(tw, t);
-    const int64_t U = jobs.total, G = gridDim.x;
-    // XCD-ordered: blocks with neighbouring unit ranges (the right-hand
-    // sides of one column block, then neighbouring column blocks, whose
-    // panel segments share 128-byte lines) run on one XCD
-    const int w = xcd_order(blockIdx.x, (int)G);
-    const int u0 = (int)((int64_t)w * U / G), u1 = (int)((int64_t)(w + 1) * U / G);
-    // unit u -> (job k, key = cb * nrhs + q, layer l)
-    auto decode = [&](int u, int& k, int& key, int& l) {
-        k = find_job(jobs, u);
-        const int lu = u - jobs.j[k].begin;
-        l = lu % jobs.j[k].nl;
-        key = lu / jobs.j[k].nl;
-    };
-    cT<T> tn[8];
-    auto load_spec = [&](int u) {
-        int k, key, l;
-        decode(u, k, key, l);
-        const ColJob& J = jobs.j[k];
-        const int cb = key / J.nrhs;
-        const int col = cb * C::CPW + cl;
-        const int ccol = col < J.ncols ? col : 0;
-        if constexpr (SF == FORM_COMPLEX) {
-            const cT<T>* sp = (const cT<T>*)J.spec + ((int64_t)(J.r0 + l) * J.ncols + ccol) * N;
-#pragma unroll
-            for (int m = 0; m < 8; ++m) tn[m] = sp[t + m * TPL];
-        } else {
-            load_real_even<T, N>(tn, J, J.r0 + l, ccol, cb == 0 && cl == 0, t);
-        }
-    };
-    int cur_k = -1, cur_key = -1;
-    cT<T> rh[8];
-    constexpr bool PIPE = true;
-    if (PIPE && u0 < u1) load_spec(u0);
-    for (int u = u0; u < u1; ++u) {
-        if (!PIPE) load_spec(u);
-        int k, key, l;
-        decode(u, k, key, l);
-        const ColJob& J = jobs.j[k];
-        const int cb = key / J.nrhs, q = key % J.nrhs;
-        const int col = cb * C::CPW + cl;
-        const bool ok = col < J.ncols;
-        const bool packed_blk = cb == 0;
-        const bool packed = packed_blk && cl == 0;
-        cT<T> tv[8];
-#pragma unroll
-        for (int m = 0; m < 8; ++m) tv[m] = tn[m];
-        if (PIPE && u + 1 < u1) load_spec(u + 1);
-        if (k != cur_k || key != cur_key) {
-            // R^ of this column: FFT_y of the packed row-pass output of the data
-            const cT<T>* rs = (const cT<T>*)J.a + (int64_t)q * J.ncols * J.lda;
-#pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                const int y = t + m * TPL;
-                rh[m] = (ok && y < J.na) ? rs[pidx(col, y, J.ncols)] : mk<T>(0, 0);
-            }
-            if (J.na <= N / 2) fft_line<T, N, -1, true>(rh, xl, twl, t);
-            else fft_line<T, N, -1, false>(rh, xl, twl, t);
-            if constexpr (SF == FORM_REAL_EVEN) {
-                // conj(T^) R^ = R conj(P) R^: apply conj(P) once.  The packed
-                // column keeps conj(P) A in rh and conj(P) B in its second LDS
-                // buffer (read back by the same thread only).
-                if (packed_blk) {
-                    stage_line<T, N>(rh, xl, t, packed);
-                    if (packed) {
-#pragma unroll
-                        for (int m = 0; m < 8; ++m) {
-                            const cT<T> rr = xl[mirror_idx<N>(t, m)];
-                            const cT<T> ph = phase<T>(0, 2, (int)(((int64_t)J.py * (t + m * TPL)) & (N - 1)), N);
-                            const cT<T> a = cmulc<T>(herm_a<T>(rh[m], rr), ph);
-                            xs2[lpad(t + m * TPL)] = cmulc<T>(herm_b<T>(rh[m], rr), ph);
-                            rh[m] = a;
-                        }
-                    }
-                }
-                if (!packed) {
-                    const int ax = (int)(((int64_t)J.px * (ok ? col : 0)) & (2 * J.ncols - 1));
-#pragma unroll
-                    for (int m = 0; m < 8; ++m)
-                        rh[m] = cmulc<T>(rh[m],
-                                         phase<T>(ax, 2 * J.ncols, (int)(((int64_t)J.py * (t + m * TPL)) & (N - 1)), N));
-                }
-            }
-            cur_k = k;
-            cur_key = key;
-        }
-        cT<T> v[8];
-        if constexpr (SF == FORM_COMPLEX) {
-#pragma unroll
-            for (int m = 0; m < 8; ++m) v[m] = cmulc<T>(rh[m], tv[m]);
-            if (packed_blk) {
-                stage_pair<T, N>(rh, tv, xl, xs2, t, packed);
-                if (packed) {
-                    // column 0: conj(T0) R0 + i conj(T1) R1
-#pragma unroll
-                    for (int m = 0; m < 8; ++m) {
-                        const int mi = mirror_idx<N>(t, m);
-                        const cT<T> rr = xl[mi], tr = xs2[mi];
-                        const cT<T> p0 = cmulc<T>(herm_a<T>(rh[m], rr), herm_a<T>(tv[m], tr));
-                        const cT<T> p1 = cmulc<T>(herm_b<T>(rh[m], rr), herm_b<T>(tv[m], tr));
-                        v[m] = mk<T>(p0.x - p1.y, p0.y + p1.x);
-                    }
-                }
-            }
-        } else {
-            if (packed) {
-                // R(0) A' + i (-1)^pxl R(Nx/2) B'
-#pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    const cT<T> b = xs2[lpad(t + m * TPL)];
-                    v[m] = mk<T>(tv[m].x * rh[m].x - tv[m].y * b.y, tv[m].x * rh[m].y + tv[m].y * b.x);
-                }
-            } else {
-#pragma unroll
-                for (int m = 0; m < 8; ++m) v[m] = mk<T>(tv[m].x * rh[m].x, tv[m].x * rh[m].y);
-            }
-        }
-        fft_line<T, N, +1, false>(v, xl, twl, t);
-        if (ok) {
-            cT<T>* zs = (cT<T>*)J.b + ((int64_t)q * J.nl + l) * J.ncols * J.ldb;
-#pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                const int y = t + m * TPL;
-                if (y < J.nb) zs[pidx(col, y, J.ncols)] = v[m];
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// launchers (dispatch on the transform length, column tile and form)
-// ---------------------------------------------------------------------------
-template <typename T, int ACC, int SF>
-static hipError_t launch_fwd_form(int N, int tile, const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
-{
-#define L_FWD(NN)                                                                          \
-    if constexpr (col_tile2_fits<T, NN>()) {                                               \
-        if (tile == 2) {                                                                   \
-            hipLaunchKernelGGL((k_cols_fwd_mac<T, NN, 1, ACC, 2, SF>), dim3(jobs.total),   \
-                               dim3(ColCfg<NN, 2>::THREADS), 0, s, jobs, tw);              \
-            break;                                                                         \
-        }                                                                                  \
-    }                                                                                      \
-    hipLaunchKernelGGL((k_cols_fwd_mac<T, NN, 1, ACC, 1, SF>), dim3(jobs.total), dim3(ColCfg<NN, 1>::THREADS), \
-                       0, s, jobs, tw);
-    BTTB_LEN_SWITCH(N, L_FWD)
-#undef L_FWD
-    return hipGetLastError();
-}
+// defined in cols_impl.h, instantiated per length in bttb_cols_*.hip
+template <typename T, int ACC, int NN>
+hipError_t cols_fwd_n(int tile, int form, const ColJobs& jobs, const cT<T>* tw, hipStream_t s);
+template <typename T, int NN>
+hipError_t cols_fin_n(int tile, int form, const ColJobs& jobs, const cT<T>* tw, hipStream_t s);
+template <typename T, int NN>
+hipError_t cols_tr_n(int tile, int form, const ColJobs& jobs, const cT<T>* tw, hipStream_t s);
 
 template <typename T, int ACC>
 hipError_t launch_cols_fwd(int N, int tile, int form, const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
 {
     if (jobs.total <= 0) return hipSuccess;
-    return form == FORM_REAL_EVEN ? launch_fwd_form<T, ACC, FORM_REAL_EVEN>(N, tile, jobs, tw, s)
-                                  : launch_fwd_form<T, ACC, FORM_COMPLEX>(N, tile, jobs, tw, s);
-}
-
-template <typename T, int SF>
-static hipError_t launch_fin_form(int N, int tile, const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
-{
-#define L_FIN(NN)                                                                          \
-    if constexpr (col_tile2_fits<T, NN>()) {                                               \
-        if (tile == 2) {                                                                   \
-            hipLaunchKernelGGL((k_cols_fwd_fin<T, NN, 2, SF>), dim3(jobs.total),           \
-                               dim3(ColCfg<NN, 2>::THREADS), 0, s, jobs, tw);              \
-            break;                                                                         \
-        }                                                                                  \
-    }                                                                                      \
-    hipLaunchKernelGGL((k_cols_fwd_fin<T, NN, 1, SF>), dim3(jobs.total), dim3(ColCfg<NN, 1>::THREADS), \
-                       0, s, jobs, tw);
-    BTTB_LEN_SWITCH(N, L_FIN)
-#undef L_FIN
-    return hipGetLastError();
+#define L_FWD(NN) return cols_fwd_n<T, ACC, NN>(tile, form, jobs, tw, s)
+    BTTB_LEN_SWITCH(N, L_FWD)
+#undef L_FWD
+    return hipErrorInvalidValue;
 }
 
 template <typename T>
 hipError_t launch_cols_fwd_fin(int N, int tile, int form, const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
 {
     if (jobs.total <= 0) return hipSuccess;
-    return form == FORM_REAL_EVEN ? launch_fin_form<T, FORM_REAL_EVEN>(N, tile, jobs, tw, s)
-                                  : launch_fin_form<T, FORM_COMPLEX>(N, tile, jobs, tw, s);
-}
-
-// persistent: as many blocks as are resident at once (at most one per unit)
-template <typename T, int NN, int CM, int SF>
-static void launch_tr_n(const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
-{
-    // thread-safe one-time initialisation (function-local static)
-    static const int resident = resident_blocks((const void*)k_cols_tr_mac<T, NN, 1, CM, SF>, ColCfg<NN, CM>::THREADS);
-    hipLaunchKernelGGL((k_cols_tr_mac<T, NN, 1, CM, SF>), dim3(std::min(jobs.total, resident)),
-                       dim3(ColCfg<NN, CM>::THREADS), 0, s, jobs, tw);
-}
-
-template <typename T, int SF>
-static hipError_t launch_tr_form(int N, int tile, const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
-{
-#define L_TR(NN)                                                                           \
-    if constexpr (col_tile2_fits<T, NN>()) {                                               \
-        if (tile == 2) {                                                                   \
-            launch_tr_n<T, NN, 2, SF>(jobs, tw, s);                                        \
-            break;                                                                         \
-        }                                                                                  \
-    }                                                                                      \
-    launch_tr_n<T, NN, 1, SF>(jobs, tw, s);
-    BTTB_LEN_SWITCH(N, L_TR)
-#undef L_TR
-    return hipGetLastError();
+#define L_FIN(NN) return cols_fin_n<T, NN>(tile, form, jobs, tw, s)
+    BTTB_LEN_SWITCH(N, L_FIN)
+#undef L_FIN
+    return hipErrorInvalidValue;
 }
 
 template <typename T>
 hipError_t launch_cols_tr(int N, int tile, int form, const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
 {
     if (jobs.total <= 0) return hipSuccess;
-    return form == FORM_REAL_EVEN ? launch_tr_form<T, FORM_REAL_EVEN>(N, tile, jobs, tw, s)
-                                  : launch_tr_form<T, FORM_COMPLEX>(N, tile, jobs, tw, s);
+#define L_TR(NN) return cols_tr_n<T, NN>(tile, form, jobs, tw, s)
+    BTTB_LEN_SWITCH(N, L_TR)
+#undef L_TR
+    return hipErrorInvalidValue;
 }
 
 template hipError_t launch_cols_fwd<double, ACC_PLAIN>(int, int, int, const ColJobs&, const double2*, hipStream_t);

@@ -42,6 +42,24 @@ int next_pow2(int64_t v)
     while (p < v) p <<= 1;
     return (int)p;
 }
+// Transform lengths the kernels are built for: powers of two in [8, 4096]
+// (8 points per thread) and 2^a 3^b, b = 1 or 2, in [96, 3072] (12 points per
+// thread), ascending.
+constexpr int kFftLens[] = {8, 16, 32, 64, 96, 128, 144, 192, 256, 288, 384, 512, 576,
+                            768, 1024, 1152, 1536, 2048, 2304, 3072, 4096};
+bool fft_len_ok(int64_t n)
+{
+    for (int v : kFftLens)
+        if (v == n) return true;
+    return false;
+}
+// smallest supported length >= n (0 if none)
+int fft_len_at_least(int64_t n)
+{
+    for (int v : kFftLens)
+        if (v >= n) return v;
+    return 0;
+}
 
 }  // namespace
 
@@ -127,13 +145,29 @@ bttb_status validate_and_fill(const bttb_problem_desc* d, bttb_plan_s* P)
     const int64_t minx = std::max<int64_t>(8, d->sx + nx - 1), miny = std::max<int64_t>(8, d->sy + ny - 1);
     int64_t Nx = d->nx_fft, Ny = d->ny_fft;
     if (Nx < 0 || Ny < 0) return fail(BTTB_ERR_INVALID_VALUE, "nx_fft, ny_fft must be >= 0");
-    if (Nx == 0) Nx = next_pow2(minx);
-    if (Ny == 0) Ny = next_pow2(miny);
+    // default: the smallest supported length (any N >= s + n - 1 holds the
+    // circulant, Sec. 3; the zeros fill the gap); for the real even form (the
+    // gravity kernel in the automatic form, or that form asked for), the
+    // smallest that also holds the centred even generator,
+    // N >= 2 (s - 1 + max(p_L, p_R)) + 1, so that its four times smaller
+    // spectra apply
+    const bool want_even = (d->problem == BTTB_GRAVITY_GZ && d->spectrum_form == BTTB_SPECTRUM_AUTO) ||
+                           d->spectrum_form == BTTB_SPECTRUM_REAL_EVEN;
+    const int64_t evx = 2 * ((int64_t)d->sx - 1 + std::max(d->pxl, d->pxr)) + 1;
+    const int64_t evy = 2 * ((int64_t)d->sy - 1 + std::max(d->pyl, d->pyr)) + 1;
+    auto pick = [](int64_t lo, int64_t even_lo) {
+        const int64_t a = lo <= 4096 ? fft_len_at_least(lo) : next_pow2(lo);
+        if (even_lo <= lo || even_lo > 4096) return a;
+        return (int64_t)fft_len_at_least(even_lo);
+    };
+    if (Nx == 0) Nx = pick(minx, want_even ? evx : 0);
+    if (Ny == 0) Ny = pick(miny, want_even ? evy : 0);
     if (Nx < minx || Ny < miny)
         return fail(BTTB_ERR_INVALID_VALUE, "nx_fft, ny_fft must be >= max(8, s + n - 1) (no circular aliasing)");
-    if (!is_pow2(Nx) || !is_pow2(Ny))
-        return fail(BTTB_ERR_UNSUPPORTED, "FFT lengths must be powers of two");
     if (Nx > 4096 || Ny > 4096) return fail(BTTB_ERR_UNSUPPORTED, "FFT lengths above 4096 are not supported");
+    if (!fft_len_ok(Nx) || !fft_len_ok(Ny))
+        return fail(BTTB_ERR_UNSUPPORTED,
+                    "FFT lengths must be powers of two in [8, 4096] or 2^a 3^b (b = 1, 2) in [96, 3072]");
 
     P->d = *d;
     P->d.z_edges = nullptr;
@@ -423,13 +457,14 @@ struct ColStage {
     // units: work items per (right-hand side, column block): the layer
     // ranges of the forward kernel (one block each), the layers of the
     // persistent transpose kernel, 1 for the forward finishing kernel
-    void add(const ColKey& key, const cT<T>* twp, const ColJob& j, int units = 1)
+    // lines: columns per block (0: the column kernels' block of key.tile)
+    void add(const ColKey& key, const cT<T>* twp, const ColJob& j, int units = 1, int lines = 0)
     {
         size_t g = 0;
         while (g < keys.size() && !(keys[g] == key)) ++g;
         if (g == keys.size()) { keys.push_back(key); jobs.emplace_back(); work.emplace_back(); tw.push_back(twp); }
         ColJob jj = j;
-        const int cb = col_block_lines<T>(key.N, key.tile);
+        const int cb = lines > 0 ? lines : col_block_lines<T>(key.N, key.tile);
         jj.nbx = (j.ncols + cb - 1) / cb;
         jobs[g].push_back(jj);
         work[g].push_back((int64_t)jj.nbx * j.nrhs * units);
@@ -550,7 +585,7 @@ bttb_status run_forward(const std::vector<Item>& items, hipStream_t s, hipEvent_
         cj.ns = fwd_split(P, all_blocks);
         cj.p = it.ws + L.fwd_p;
         c2.add(key, tw_y<T>(P, it.spec), cj, cj.ns);
-        if (cj.ns > 1) c2f.add(ColKey{P->Ny, 0, P->col_tile, P->form}, tw_y<T>(P, it.spec), cj);
+        if (cj.ns > 1) c2f.add(ColKey{P->Ny, 0, 0, P->form}, tw_y<T>(P, it.spec), cj, 1, fin_block_lines(P->Ny));
         r3.add(P->Nx, P->row_tile, tw_x<T>(P, it.spec),
                RowJob{Y, it.out, P->ncols * psy, 0, (int64_t)P->sx * P->sy, P->sx, P->sx, P->sy, 0, 0},
                it.nrhs);
@@ -1258,6 +1293,32 @@ TuneScratch tune_layout(const bttb_plan_s* P, int nrhs)
     return L;
 }
 
+// FFT lengths the autotuner tries along one axis: the plan's default, the
+// smallest supported length and the smallest power of two that hold the
+// circulant (an axis with an explicit length keeps it)
+std::vector<int> tune_lengths(int64_t requested, int64_t s, int64_t n, int chosen)
+{
+    if (requested > 0) return {chosen};
+    const int64_t lo = std::max<int64_t>(8, s + n - 1);
+    std::vector<int> v{chosen};
+    for (int64_t c : {(int64_t)fft_len_at_least(lo), (int64_t)next_pow2(lo)})
+        if (c > 0 && c <= 4096 && std::find(v.begin(), v.end(), (int)c) == v.end()) v.push_back((int)c);
+    return v;
+}
+// descriptors of every candidate (Nx, Ny) pair, the default first
+std::vector<bttb_problem_desc> tune_candidates(const bttb_problem_desc& d0, const bttb_plan_s& base)
+{
+    std::vector<bttb_problem_desc> out;
+    for (int nx : tune_lengths(d0.nx_fft, base.sx, base.nx, base.Nx))
+        for (int ny : tune_lengths(d0.ny_fft, base.sy, base.ny, base.Ny)) {
+            bttb_problem_desc d = d0;
+            d.nx_fft = nx;
+            d.ny_fft = ny;
+            out.push_back(d);
+        }
+    return out;
+}
+
 std::string tune_cache_path()
 {
     if (const char* e = std::getenv("BTTB_TUNE_CACHE")) return e;
@@ -1278,13 +1339,14 @@ std::string tune_key(const bttb_plan_s* P, int nrhs)
     for (char& c : arch)
         if (c == ' ') c = '_';
     std::ostringstream k;
-    k << "v2 " << P->form << ' ' << P->d.problem << ' ' << P->d.precision << ' ' << P->sx << ' ' << P->sy << ' ' << P->nz << ' '
+    k << "v3 " << P->form << ' ' << P->d.problem << ' ' << P->d.precision << ' ' << P->sx << ' ' << P->sy << ' ' << P->nz << ' '
       << P->d.pxl << ' ' << P->d.pxr << ' ' << P->d.pyl << ' ' << P->d.pyr << ' ' << P->Nx << ' ' << P->Ny << ' '
       << P->acc << ' ' << nrhs << ' ' << arch << ' ' << ncu;
     return k.str();
 }
 
-bool tune_lookup(const std::string& key, int v[3], float* ms)
+// cached choice: layer_chunk, row_tile, col_tile, nx_fft, ny_fft
+bool tune_lookup(const std::string& key, int v[5], float* ms)
 {
     std::ifstream f(tune_cache_path());
     std::string line;
@@ -1292,15 +1354,15 @@ bool tune_lookup(const std::string& key, int v[3], float* ms)
         const size_t bar = line.find('|');
         if (bar == std::string::npos || line.substr(0, bar) != key) continue;
         std::istringstream is(line.substr(bar + 1));
-        if (is >> v[0] >> v[1] >> v[2] >> *ms) return true;
+        if (is >> v[0] >> v[1] >> v[2] >> v[3] >> v[4] >> *ms) return true;
     }
     return false;
 }
 
-void tune_store(const std::string& key, const int v[3], float ms)
+void tune_store(const std::string& key, const int v[5], float ms)
 {
     std::ofstream f(tune_cache_path(), std::ios::app);
-    if (f) f << key << '|' << v[0] << ' ' << v[1] << ' ' << v[2] << ' ' << ms << '\n';
+    if (f) f << key << '|' << v[0] << ' ' << v[1] << ' ' << v[2] << ' ' << v[3] << ' ' << v[4] << ' ' << ms << '\n';
 }
 
 }  // namespace
@@ -1318,7 +1380,13 @@ bttb_status bttb_autotune_query(const bttb_problem_desc* desc, int32_t nrhs, siz
         d.layer_chunk = 0;
         bttb_status st = validate_and_fill(&d, &P);
         if (st != BTTB_OK) return st;
-        *scratch_bytes = tune_layout(&P, nrhs).total;
+        size_t need = 0;
+        for (const bttb_problem_desc& c : tune_candidates(d, P)) {
+            bttb_plan_s Q;
+            if ((st = validate_and_fill(&c, &Q)) != BTTB_OK) return st;
+            need = std::max(need, tune_layout(&Q, nrhs).total);
+        }
+        *scratch_bytes = need;
         return BTTB_OK;
     } catch (...) {
         return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_autotune_query");
@@ -1340,87 +1408,105 @@ bttb_status bttb_autotune(const bttb_problem_desc* desc, int32_t nrhs, void* scr
         d0.col_tile = 0;
         bttb_status st = validate_and_fill(&d0, &base);
         if (st != BTTB_OK) return st;
-        const TuneScratch L = tune_layout(&base, nrhs);
-        if (scratch_bytes < L.total) return fail(BTTB_ERR_WORKSPACE_TOO_SMALL, "scratch smaller than bttb_autotune_query reports");
+        const std::vector<bttb_problem_desc> cands = tune_candidates(d0, base);
+        size_t need = 0;
+        for (const bttb_problem_desc& c : cands) {
+            bttb_plan_s Q;
+            if ((st = validate_and_fill(&c, &Q)) != BTTB_OK) return st;
+            need = std::max(need, tune_layout(&Q, nrhs).total);
+        }
+        if (scratch_bytes < need) return fail(BTTB_ERR_WORKSPACE_TOO_SMALL, "scratch smaller than bttb_autotune_query reports");
         *tuned = *desc;
         const std::string key = tune_key(&base, nrhs);
-        int best[3];
+        int best[5];
         float bms = 0.f;
         if (tune_lookup(key, best, &bms)) {
             tuned->layer_chunk = best[0];
             tuned->row_tile = best[1];
             tuned->col_tile = best[2];
+            tuned->nx_fft = best[3];
+            tuned->ny_fft = best[4];
             if (best_ms) *best_ms = bms;
             return BTTB_OK;
         }
         hipStream_t s = (hipStream_t)stream;
         char* base_ptr = (char*)scratch;
-        char* spec = base_ptr + L.spec;
-        char* ws = base_ptr + L.ws;
-        // spectra do not depend on the tuning choices: generate once (a user
-        // table plan has no entries here; its timing does not depend on the
-        // values, so its spectra are zeros)
-        if (base.d.problem == BTTB_USER_TABLE) {
-            st = hip_check(hipMemsetAsync(spec, 0, base.spec_bytes, s), "memset");
-            if (st == BTTB_OK)
-                st = hip_check(launch_twiddles((double2*)(spec + base.off_tw64x),
-                                               base.fp64 ? nullptr : (float2*)(spec + base.off_twx), base.Nx, s),
-                               "twiddles x");
-            if (st == BTTB_OK)
-                st = hip_check(launch_twiddles((double2*)(spec + base.off_tw64y),
-                                               base.fp64 ? nullptr : (float2*)(spec + base.off_twy), base.Ny, s),
-                               "twiddles y");
-        } else
-            st = base.fp64 ? run_generate<double>(&base, spec, ws, s) : run_generate<float>(&base, spec, ws, s);
-        if (st != BTTB_OK) return st;
-        if ((st = hip_check(hipMemsetAsync(base_ptr + L.m, 0, L.d - L.m, s), "memset")) != BTTB_OK) return st;
-        if ((st = hip_check(hipMemsetAsync(base_ptr + L.r, 0, L.mt - L.r, s), "memset")) != BTTB_OK) return st;
-        std::vector<int> chunks{0};
-        for (int c : {8, 16, 32})
-            if (c < base.nz) chunks.push_back(c);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if ((st = hip_check(hipEventCreate(&e0), "event")) != BTTB_OK) return st;
         if ((st = hip_check(hipEventCreate(&e1), "event")) != BTTB_OK) { (void)hipEventDestroy(e0); return st; }
         float best_t = -1.f;
-        for (int rt : {4, 2, 8})
-            for (int ct : {1, 2})
-                for (int ch : chunks) {
-                    if (st != BTTB_OK) break;
-                    bttb_plan_s P;
-                    bttb_problem_desc d = d0;
-                    d.layer_chunk = ch;
-                    d.row_tile = rt;
-                    d.col_tile = ct;
-                    if ((st = validate_and_fill(&d, &P)) != BTTB_OK) break;
-                    auto once = [&]() -> bttb_status {
-                        bttb_status r = P.fp64 ? run_single<double>(true, &P, spec, base_ptr + L.m, base_ptr + L.d, nrhs, ws, s)
-                                               : run_single<float>(true, &P, spec, base_ptr + L.m, base_ptr + L.d, nrhs, ws, s);
-                        if (r != BTTB_OK) return r;
-                        return P.fp64 ? run_single<double>(false, &P, spec, base_ptr + L.r, base_ptr + L.mt, nrhs, ws, s)
-                                      : run_single<float>(false, &P, spec, base_ptr + L.r, base_ptr + L.mt, nrhs, ws, s);
-                    };
-                    if ((st = once()) != BTTB_OK) break;
-                    if ((st = hip_check(hipEventRecord(e0, s), "event record")) != BTTB_OK) break;
-                    for (int rep = 0; rep < 3 && st == BTTB_OK; ++rep) st = once();
-                    if (st != BTTB_OK) break;
-                    if ((st = hip_check(hipEventRecord(e1, s), "event record")) != BTTB_OK) break;
-                    if ((st = hip_check(hipEventSynchronize(e1), "event synchronize")) != BTTB_OK) break;
-                    float t = 0.f;
-                    if ((st = hip_check(hipEventElapsedTime(&t, e0, e1), "elapsed")) != BTTB_OK) break;
-                    t /= 3.f;
-                    if (best_t < 0.f || t < best_t) {
-                        best_t = t;
-                        best[0] = ch;
-                        best[1] = rt;
-                        best[2] = ct;
+        for (const bttb_problem_desc& dc : cands) {
+            if (st != BTTB_OK) break;
+            bttb_plan_s cb;
+            if ((st = validate_and_fill(&dc, &cb)) != BTTB_OK) break;
+            const TuneScratch L = tune_layout(&cb, nrhs);
+            char* spec = base_ptr + L.spec;
+            char* ws = base_ptr + L.ws;
+            // spectra do not depend on the tile choices: generate once per
+            // length pair (a user table plan has no entries here; its timing
+            // does not depend on the values, so its spectra are zeros)
+            if (cb.d.problem == BTTB_USER_TABLE) {
+                st = hip_check(hipMemsetAsync(spec, 0, cb.spec_bytes, s), "memset");
+                if (st == BTTB_OK)
+                    st = hip_check(launch_twiddles((double2*)(spec + cb.off_tw64x),
+                                                   cb.fp64 ? nullptr : (float2*)(spec + cb.off_twx), cb.Nx, s),
+                                   "twiddles x");
+                if (st == BTTB_OK)
+                    st = hip_check(launch_twiddles((double2*)(spec + cb.off_tw64y),
+                                                   cb.fp64 ? nullptr : (float2*)(spec + cb.off_twy), cb.Ny, s),
+                                   "twiddles y");
+            } else
+                st = cb.fp64 ? run_generate<double>(&cb, spec, ws, s) : run_generate<float>(&cb, spec, ws, s);
+            if (st != BTTB_OK) break;
+            if ((st = hip_check(hipMemsetAsync(base_ptr + L.m, 0, L.d - L.m, s), "memset")) != BTTB_OK) break;
+            if ((st = hip_check(hipMemsetAsync(base_ptr + L.r, 0, L.mt - L.r, s), "memset")) != BTTB_OK) break;
+            std::vector<int> chunks{0};
+            for (int c : {8, 16, 32})
+                if (c < cb.nz) chunks.push_back(c);
+            for (int rt : {4, 2, 8})
+                for (int ct : {1, 2})
+                    for (int ch : chunks) {
+                        if (st != BTTB_OK) break;
+                        bttb_plan_s P;
+                        bttb_problem_desc d = dc;
+                        d.layer_chunk = ch;
+                        d.row_tile = rt;
+                        d.col_tile = ct;
+                        if ((st = validate_and_fill(&d, &P)) != BTTB_OK) break;
+                        auto once = [&]() -> bttb_status {
+                            bttb_status r = P.fp64 ? run_single<double>(true, &P, spec, base_ptr + L.m, base_ptr + L.d, nrhs, ws, s)
+                                                   : run_single<float>(true, &P, spec, base_ptr + L.m, base_ptr + L.d, nrhs, ws, s);
+                            if (r != BTTB_OK) return r;
+                            return P.fp64 ? run_single<double>(false, &P, spec, base_ptr + L.r, base_ptr + L.mt, nrhs, ws, s)
+                                          : run_single<float>(false, &P, spec, base_ptr + L.r, base_ptr + L.mt, nrhs, ws, s);
+                        };
+                        if ((st = once()) != BTTB_OK) break;
+                        if ((st = hip_check(hipEventRecord(e0, s), "event record")) != BTTB_OK) break;
+                        for (int rep = 0; rep < 3 && st == BTTB_OK; ++rep) st = once();
+                        if (st != BTTB_OK) break;
+                        if ((st = hip_check(hipEventRecord(e1, s), "event record")) != BTTB_OK) break;
+                        if ((st = hip_check(hipEventSynchronize(e1), "event synchronize")) != BTTB_OK) break;
+                        float t = 0.f;
+                        if ((st = hip_check(hipEventElapsedTime(&t, e0, e1), "elapsed")) != BTTB_OK) break;
+                        t /= 3.f;
+                        if (best_t < 0.f || t < best_t) {
+                            best_t = t;
+                            best[0] = ch;
+                            best[1] = rt;
+                            best[2] = ct;
+                            best[3] = dc.nx_fft;
+                            best[4] = dc.ny_fft;
+                        }
                     }
-                }
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (st != BTTB_OK) return st;
         tuned->layer_chunk = best[0];
         tuned->row_tile = best[1];
         tuned->col_tile = best[2];
+        tuned->nx_fft = best[3];
+        tuned->ny_fft = best[4];
         if (best_ms) *best_ms = best_t;
         tune_store(key, best, best_t);
         return BTTB_OK;

@@ -109,6 +109,8 @@ hipError_t launch_generate(const GenParams& P, int r0, int nl, double* out, hipS
 // (column tile 1 or 2 times the default) of the kernels for length N
 template <typename T> int row_group_rows(int N, int tile);
 template <typename T> int col_block_lines(int N, int tile);
+// columns per block of the forward's finishing kernel for length N
+int fin_block_lines(int N);
 template <typename TI, typename T>
 hipError_t launch_rows_r2c(int N, int tile, const RowJobs& jobs, const cT<T>* tw, hipStream_t s);
 template <typename T>

@@ -37,16 +37,37 @@ template <typename JT> __device__ __forceinline__ int find_job(const JT& js, int
 #define BTTB_COL_WAVES 2
 #endif
 // CM: multiplier of the columns per block (a tuning choice, 1 or 2)
+// Lines per block of 256 threads, or of 192 where a line's thread count
+// divides 192 but not 256 (12-point lines of 12, 24, 48, 96 or 192 threads),
+// so that a block is whole wavefronts.
+constexpr int lines_per_block(int tpl)
+{
+    return tpl >= 256 ? 1 : (256 % tpl == 0 ? 256 / tpl : (192 % tpl == 0 ? 192 / tpl : 256 / tpl));
+}
 template <int N, int CM = 1> struct ColCfg {
-    static constexpr int TPL = N / 8;
-    static constexpr int CPW = (TPL >= 256 ? 1 : 256 / TPL) * CM;   // columns per block
+    static constexpr int TPL = FftShape<N>::TPL;
+    static constexpr int CPW = lines_per_block(TPL) * CM;   // columns per block
     static constexpr int THREADS = CPW * TPL;
 };
 
-// a column tile of 2 is used only where its LDS fits in 160 KB
+// Lines per block of the forward's finishing kernel (which adds the depth
+// ranges' partial sums): about one wavefront per block, since the kernel is
+// bound by the latency of those loads and wants many small blocks.
+#ifndef BTTB_FIN_WAVE
+#define BTTB_FIN_WAVE 1
+#endif
+template <int N> struct FinCfg {
+    static constexpr int TPL = FftShape<N>::TPL;
+    static constexpr int CPW = BTTB_FIN_WAVE ? (TPL >= 64 ? 1 : 64 / TPL) : lines_per_block(TPL);
+    static constexpr int THREADS = CPW * TPL;
+};
+
+// a column tile of 2 is used only where its LDS (line buffers and, for
+// 12-point lines, the twiddle table) fits in 160 KB
 template <typename T, int NN> constexpr bool col_tile2_fits()
 {
-    return (ColCfg<NN, 2>::CPW + 1) * lds_line_elems(NN) * (int)sizeof(cT<T>) <= 160 * 1024;
+    return ((ColCfg<NN, 2>::CPW + 1) * lds_line_elems(NN) + (FftShape<NN>::POW2 ? 0 : TableTwiddles<T, NN>::size())) *
+               (int)sizeof(cT<T>) <= 160 * 1024;
 }
 
 #define BTTB_LEN_SWITCH(n, MACRO) \
@@ -61,6 +82,17 @@ template <typename T, int NN> constexpr bool col_tile2_fits()
     case 1024: MACRO(1024); break;\
     case 2048: MACRO(2048); break;\
     case 4096: MACRO(4096); break;\
+    case 96: MACRO(96); break;    \
+    case 144: MACRO(144); break;  \
+    case 192: MACRO(192); break;  \
+    case 288: MACRO(288); break;  \
+    case 384: MACRO(384); break;  \
+    case 576: MACRO(576); break;  \
+    case 768: MACRO(768); break;  \
+    case 1152: MACRO(1152); break;\
+    case 1536: MACRO(1536); break;\
+    case 2304: MACRO(2304); break;\
+    case 3072: MACRO(3072); break;\
     default: return hipErrorInvalidValue; }
 
 // blocks of `kernel` that are resident on the whole current device at once

@@ -410,9 +410,9 @@ class Batch:
 
 def bttb_autotune(problem: dict, precision: str = "fp32", nrhs: int = 1, accumulation: str = "default",
                   stream=None):
-    """Time the candidate kernel configurations for this problem on the
-    current device (or read them from the on-disk cache) and return
-    (problem dict with layer_chunk / row_tile / col_tile filled in, ms per
+    """Time the candidate configurations for this problem on the current
+    device (or read them from the on-disk cache) and return (problem dict with
+    nx_fft / ny_fft / layer_chunk / row_tile / col_tile filled in, ms per
     forward + transpose pair)."""
     L = _lib.load()
     d, keep = make_desc(problem, precision, accumulation)
@@ -425,5 +425,6 @@ def bttb_autotune(problem: dict, precision: str = "fp32", nrhs: int = 1, accumul
                                            ctypes.byref(out), ctypes.byref(ms)))
     del keep, scratch
     tuned = dict(problem)
-    tuned.update(layer_chunk=out.layer_chunk, row_tile=out.row_tile, col_tile=out.col_tile)
+    tuned.update(layer_chunk=out.layer_chunk, row_tile=out.row_tile, col_tile=out.col_tile,
+                 nx_fft=out.nx_fft, ny_fft=out.ny_fft)
     return tuned, ms.value

@@ -57,7 +57,7 @@ def _create(prob, prec="fp32", **over):
 @pytest.mark.parametrize("field,value,status", [
     ("sx", 0, 1), ("sy", -3, 1), ("nz", 0, 1), ("pxl", -1, 1), ("dx", 0.0, 1), ("dy", float("nan"), 1),
     ("dz", -1.0, 1), ("station_height", -1.0, 1), ("problem", 7, 1), ("problem", 3, 1), ("precision", 3, 1),
-    ("nx", 17, 1), ("nx_fft", 16, 1), ("nx_fft", 96, 3), ("ny_fft", 8192, 3), ("accumulation", 9, 1),
+    ("nx", 17, 1), ("nx_fft", 16, 1), ("nx_fft", 100, 3), ("nx_fft", 432, 3), ("ny_fft", 8192, 3), ("accumulation", 9, 1),
     ("layer_chunk", -1, 1), ("row_tile", 3, 1), ("col_tile", 4, 1), ("spectrum_form", 3, 1),
 ])
 def test_invalid_descriptors_rejected(lib, field, value, status):
@@ -132,18 +132,30 @@ def test_spectrum_form_choice(lib):
         (W.problem(W.PROBE, 3, 1, 1, dx=1.0, dy=1.0, dz=1.0), "auto", "complex"),
         # equal paddings: 2 (s - 1 + p) + 1 = s + n - 1 always fits
         (W.table1_problem(3, W.GRAVITY, True), "auto", "real_even"),
-        # s + n - 1 = 15 -> N = 16, but 2 (5 - 1 + 6) + 1 = 21 > 16
-        (W.problem(W.GRAVITY, 5, 5, 2, 6, 0, 0, 0, dx=10.0, dy=10.0, dz=5.0), "auto", "complex"),
-        # the same with room: N = 32
+        # s + n - 1 = 15, but 2 (5 - 1 + 6) + 1 = 21 > 16: asked for N = 16
+        (W.problem(W.GRAVITY, 5, 5, 2, 6, 0, 0, 0, dx=10.0, dy=10.0, dz=5.0, nx_fft=16), "auto", "complex"),
+        # the same with room: N = 32, asked for or chosen by the plan
         (W.problem(W.GRAVITY, 5, 5, 2, 6, 0, 0, 0, dx=10.0, dy=10.0, dz=5.0, nx_fft=32), "auto", "real_even"),
+        (W.problem(W.GRAVITY, 5, 5, 2, 6, 0, 0, 0, dx=10.0, dy=10.0, dz=5.0), "auto", "real_even"),
         (W.small_gravity(), "complex", "complex"),
     ]
     for pr, req, got in cases:
         h = B.bttb_plan_create(dict(pr, spectrum_form=req), "fp32")
         assert B.bttb_plan_spectrum_form(h) == got, (pr, req)
         B.bttb_plan_destroy(h)
-    for pr in (W.magnetic_48x56(), W.problem(W.GRAVITY, 5, 5, 2, 6, 0, 0, 0, dx=10.0, dy=10.0, dz=5.0),
-               W.problem(W.TABLE, 5, 5, 2, 6, 0, 0, 0)):
+    # the default length of an automatic-form gravity plan admits the real
+    # even form; the complex form and the magnetic kernel take the smallest
+    pr = W.problem(W.GRAVITY, 5, 5, 2, 6, 0, 0, 0, dx=10.0, dy=10.0, dz=5.0)
+    for req, n in (("auto", 32), ("complex", 16)):
+        h = B.bttb_plan_create(dict(pr, spectrum_form=req), "fp32")
+        assert B.bttb_plan_query(h, 1)[2] == n, req
+        B.bttb_plan_destroy(h)
+    h = B.bttb_plan_create(dict(pr, kind=W.MAGNETIC, incl=60.0, decl=10.0), "fp32")
+    assert B.bttb_plan_query(h, 1)[2] == 16
+    B.bttb_plan_destroy(h)
+    # (an explicit length that cannot hold the centred generator)
+    for pr in (W.magnetic_48x56(), W.problem(W.GRAVITY, 5, 5, 2, 6, 0, 0, 0, dx=10.0, dy=10.0, dz=5.0, nx_fft=16),
+               W.problem(W.TABLE, 5, 5, 2, 6, 0, 0, 0, nx_fft=16)):
         st, h, msg = _create(dict(pr, spectrum_form="real_even"))
         assert st == 3 and h.value is None and "REAL_EVEN" in msg
     # a user table is complex unless declared even

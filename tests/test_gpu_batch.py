@@ -59,12 +59,23 @@ def test_batch48_equals_single_calls_and_replays(torch_cuda):
         assert torch.equal(extra, ref_d[rep])
 
 
+def _sampled_rel_l2(got, ref, full):
+    """Estimate of the relative 2-norm of the error over the whole vector
+    `full` from the errors on a sample of its entries."""
+    e = np.asarray(got, dtype=np.float64) - np.asarray(ref, dtype=np.float64)
+    return float(np.linalg.norm(e) * np.sqrt(full.size / e.size) / np.linalg.norm(full))
+
+
 def test_batch48_against_oracle_samples(torch_cuda):
     # every instance of the 48-instance batch (its own transform lengths and
     # spectrum forms, 4 right-hand sides) against the oracle's direct sums at
     # seeded stations and prisms: rows of G m for right-hand sides 0 and 3,
-    # columns of G^T r for right-hand sides 1 and 2 (FP32 bar 2e-5, rel-L2
-    # over the sample)
+    # columns of G^T r for right-hand sides 1 and 2.  The bar is the FP32 bar
+    # 2e-5 on the relative 2-norm over the whole output vector (Sec. 5), which
+    # the sample estimates as ||error on the sample|| sqrt(n / n_sample) over
+    # the whole vector's norm: FP32 rounding is relative to the transforms'
+    # magnitudes, so a few sampled entries far below the vector's typical
+    # size (deep layers, padding corners) must not be held to their own norm.
     torch = torch_cuda
     import oracle
     from paper_1912_06976_amd import Batch, Plan
@@ -78,18 +89,20 @@ def test_batch48_against_oracle_samples(torch_cuda):
     for k, pr in enumerate(probs):
         P = oracle_problem(pr)
         st, pq = W.fullsize_samples(pr, 3, 4, seed=6000 + 10 * k)
-        got, ref = [], []
+        got, ref, full = [], [], []
         for q in (0, 3):
             d = ds[k][q].double().cpu().numpy()
             ref += list(oracle.station_sums(P, ms[k][q].double().cpu().numpy(), st))
             got += [d[j, i] for (i, j) in st]
-        err_f = rel_l2(np.array(got), np.array(ref))
-        got, ref = [], []
+            full.append(d.ravel())
+        err_f = _sampled_rel_l2(got, ref, np.concatenate(full))
+        got, ref, full = [], [], []
         for q in (1, 2):
             t = mts[k][q].double().cpu().numpy()
             ref += list(oracle.prism_sums(P, rs[k][q].double().cpu().numpy(), pq))
             got += [t[r, qq, p] for (p, qq, r) in pq]
-        err_t = rel_l2(np.array(got), np.array(ref))
+            full.append(t.ravel())
+        err_t = _sampled_rel_l2(got, ref, np.concatenate(full))
         worst = max(worst, err_f, err_t)
         assert err_f <= 2e-5 and err_t <= 2e-5, (k, plans[k].nx_fft, plans[k].ny_fft, err_f, err_t)
     print("batch48 worst sampled rel-L2 against the oracle: %.2e" % worst, flush=True)
@@ -143,6 +156,9 @@ def test_autotune_choices_preserve_results_and_cache(torch_cuda, tmp_path, monke
     tuned, ms = bttb_autotune(pr, "fp32", nrhs=2)
     assert tuned["row_tile"] in (2, 4) and tuned["col_tile"] in (1, 2)
     assert tuned["layer_chunk"] in (0, 8, 16) and ms > 0
+    # s + n - 1 = 124 along x (128 either way) and 84 along y: 96 (2^5 3) or
+    # the power of two 128
+    assert tuned["nx_fft"] == 128 and tuned["ny_fft"] in (96, 128)
     lines = open(tmp_path / "tune.txt").read().splitlines()
     assert len(lines) == 1
     again, ms2 = bttb_autotune(pr, "fp32", nrhs=2)       # from the cache
@@ -150,8 +166,16 @@ def test_autotune_choices_preserve_results_and_cache(torch_cuda, tmp_path, monke
     assert len(open(tmp_path / "tune.txt").read().splitlines()) == 1
     ms_, rs = _inputs(torch, [Plan(pr, "fp32")], 2, 11)
     base = Plan(pr, "fp32").generate()
+    assert (base.nx_fft, base.ny_fft) == (128, 96)
     for cfg in ({"row_tile": 2, "col_tile": 2, "layer_chunk": 8}, {"row_tile": 4, "col_tile": 2},
                 {"row_tile": 8}, {"row_tile": 8, "layer_chunk": 16}, tuned):
         p = Plan(dict(pr, **cfg), "fp32").generate()
-        assert torch.equal(p.forward(ms_[0]), base.forward(ms_[0]))
-        assert torch.equal(p.transpose(rs[0]), base.transpose(rs[0]))
+        if (p.nx_fft, p.ny_fft) == (base.nx_fft, base.ny_fft):
+            # tile choices do not change the results
+            assert torch.equal(p.forward(ms_[0]), base.forward(ms_[0]))
+            assert torch.equal(p.transpose(rs[0]), base.transpose(rs[0]))
+        else:
+            # another transform length changes only the rounding
+            for a, b in ((p.forward(ms_[0]), base.forward(ms_[0])), (p.transpose(rs[0]), base.transpose(rs[0]))):
+                a, b = a.double().cpu().numpy().reshape(2, -1), b.double().cpu().numpy().reshape(2, -1)
+                assert np.max(np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)) <= 2e-5

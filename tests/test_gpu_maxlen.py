@@ -12,10 +12,10 @@ pytestmark = pytest.mark.gpu
 TOL = {"fp64": 1e-12, "fp32": 2e-5}
 
 SHAPES = {
-    # Nx = 4096 (s + n - 1 = 2206), Ny = 8
-    "gravity_x4096": W.problem(W.GRAVITY, 1100, 2, 2, 3, 4, 1, 0, dx=25.0, dy=25.0, dz=20.0),
-    # Ny = 4096 (s + n - 1 = 2064), Nx = 8
-    "magnetic_y4096": W.problem(W.MAGNETIC, 3, 1030, 2, 1, 0, 2, 3, dx=50.0, dy=50.0, dz=25.0,
+    # Nx = 4096 (s + n - 1 = 3199 > 3072, n = 2100 > 2048), Ny = 8
+    "gravity_x4096": W.problem(W.GRAVITY, 1100, 2, 2, 500, 500, 1, 0, dx=25.0, dy=25.0, dz=20.0),
+    # Ny = 4096 (s + n - 1 = 3159 > 3072, n = 2130 > 2048), Nx = 8
+    "magnetic_y4096": W.problem(W.MAGNETIC, 2, 1030, 2, 1, 0, 560, 540, dx=50.0, dy=50.0, dz=25.0,
                                 incl=55.0, decl=-25.0, field_nT=47000.0),
     # 4096 x 4096 requested for a small volume: pruned first stages both ways
     "gravity_both4096": W.problem(W.GRAVITY, 12, 9, 3, 2, 1, 0, 3, dx=50.0, dy=50.0, dz=25.0,

@@ -89,7 +89,7 @@ def test_host_library_under_sanitizers(tmp_path):
     sys.path.insert(0, ROOT)
     from paper_1912_06976_amd import build as B
     rt = _clang_asan_runtime()
-    kernel_objs = [os.path.join(B.BUILD, n) for n in ("bttb_kernels.o", "bttb_cols.o")]
+    kernel_objs = [os.path.join(B.BUILD, os.path.splitext(n)[0] + ".o") for n in B.KERNEL_SOURCES]
     if rt is None or not all(os.path.exists(o) for o in kernel_objs):
         pytest.skip("needs the clang AddressSanitizer runtime and a built library (__graft_entry__.build())")
     san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
