@@ -70,6 +70,17 @@ typedef enum {
     BTTB_USER_TABLE = 2,   /* any spatially invariant kernel: the caller supplies
                               the entries per layer and cell offset
                               (bttb_kernel_generate_table; Sec. 1 (vi))           */
+    BTTB_HESSIAN = 3,      /* scale * sum_ab w_ab U_ab: any linear combination, with
+                              the weights hessian[6], of the second derivatives
+                              U_ab = d_a d_b (integral over the prism of 1/|P - r'|)
+                              with respect to the station position P (x North,
+                              y East, z down), evaluated on the device from the
+                              closed forms of Sec. 4.2 (the user-chosen kernel of
+                              Sec. 1 (vi)): gravity-gradient components
+                              (scale 66.743 Eotvos per g/cm^3), the total-field
+                              anomaly of a remanent or induced magnetisation
+                              m (w = f m^T symmetrised; scale 100 nT per A/m, or
+                              F / (4 pi) per SI susceptibility), field components   */
     BTTB_PROBE = 99        /* test hook: entry = dx + 4096 dy + 2^24 r for the cell
                               offsets dx = p - pxl - i, dy = q - pyl - j               */
 } bttb_problem;
@@ -92,8 +103,8 @@ typedef enum { BTTB_ACC_DEFAULT = 0, BTTB_ACC_PLAIN = 1, BTTB_ACC_TWOSUM = 2, BT
  *   real values per layer, holds all of it; the paddings become a phase
  *   applied once per column.  Needs N_x >= 2 (s_x - 1 + max(pxl, pxr)) + 1
  *   and the same in y (always true for equal paddings on both sides).
- * BTTB_SPECTRUM_AUTO: REAL_EVEN where it applies (the gravity kernel), else
- *   COMPLEX.  A BTTB_USER_TABLE plan uses REAL_EVEN only when asked for (the
+ * BTTB_SPECTRUM_AUTO: REAL_EVEN where it applies (the gravity kernel, a
+ *   BTTB_HESSIAN kernel with zero off-diagonal weights), else COMPLEX.  A BTTB_USER_TABLE plan uses REAL_EVEN only when asked for (the
  *   caller declares the table even).
  * The results of both forms agree to rounding. */
 typedef enum { BTTB_SPECTRUM_AUTO = 0, BTTB_SPECTRUM_COMPLEX = 1, BTTB_SPECTRUM_REAL_EVEN = 2 } bttb_spectrum_form;
@@ -117,7 +128,8 @@ typedef struct {
     double declination_deg;    /* declination D from +x (North) towards +y (East)      */
     double field_nT;           /* field intensity F [nT], > 0 for BTTB_MAGNETIC_TMI    */
     double scale;              /* 0: default (6.6743e-3 mGal per (g/cm^3 m) for gravity,
-                                  F / (4 pi) for the magnetic kernel, 1 for the probe) */
+                                  F / (4 pi) for the magnetic kernel, 1 for the probe,
+                                  the user table and BTTB_HESSIAN)                     */
     int32_t nx_fft, ny_fft;    /* 0: the smallest supported length >= max(8, s + n - 1)
                                   (the real even form, that is the gravity kernel
                                   with spectrum_form AUTO or spectrum_form
@@ -139,6 +151,15 @@ typedef struct {
                                   columns per block of the column transforms          */
     int32_t spectrum_form;     /* bttb_spectrum_form; REAL_EVEN where it does not apply
                                   is an UNSUPPORTED error                             */
+    double hessian[6];         /* BTTB_HESSIAN: weights (w_xx, w_yy, w_zz, w_xy, w_xz,
+                                  w_yz) of U_xx, U_yy, U_zz, U_xy, U_xz, U_yz (each
+                                  off-diagonal component counted once), finite.  The
+                                  entry is evaluated with U_zz = -U_xx - U_yy
+                                  (Laplace's equation outside the prism): for a
+                                  station on a prism's top face (h = 0) this is the
+                                  limit from the air side.  With w_xy = w_xz = w_yz
+                                  = 0 the kernel is even in both cell offsets and
+                                  BTTB_SPECTRUM_AUTO uses the real even form.         */
 } bttb_problem_desc;
 
 typedef struct bttb_plan_s* bttb_plan_t;

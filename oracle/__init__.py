@@ -23,7 +23,10 @@ eq. continuousforwardmodel / eq. Gslice of Hogue, Renaut & Vatankhah):
                       and cell offset (checks user-supplied kernels).
 
 The magnetic kernel is the total-field anomaly of induced magnetisation
-(Sec. 4.2); the gravity kernel is g_z (Sec. 4.1).  Conventions (0-based):
+(Sec. 4.2); the gravity kernel is g_z (Sec. 4.1); the "hessian" kernel is a
+weighted sum of the second derivatives U_ab of the prism's potential with
+respect to the station, each from its own closed form (user-chosen kernels,
+Sec. 1 (vi)).  Conventions (0-based):
 station (i, j) at ((i+1/2) dx, (j+1/2) dy, -h); prism (p, q, r) spans
 [(p-pxl) dx, (p-pxl+1) dx] x [(q-pyl) dy, (q-pyl+1) dy] x [z_r, z_{r+1}] with z
 down (Table 3); k = j sx + i and l = r nx ny + q nx + p (eq. htilde).
@@ -43,7 +46,7 @@ _SRC = os.path.join(_HERE, "prism_oracle.c")
 _INC = os.path.join(_HERE, "prism_terms.inc")
 _LIB = os.path.join(_HERE, "_prism_oracle.so")
 
-GRAVITY, MAGNETIC, PROBE = 0, 1, 2
+GRAVITY, MAGNETIC, PROBE, HESSIAN = 0, 1, 2, 3
 
 #: gravitational constant (CODATA 2018) converted so that density in g/cm^3
 #: and lengths in m give g_z in mGal: 6.6743e-11 * 1e3 (g/cm^3 -> kg/m^3) *
@@ -72,6 +75,7 @@ class _Problem(ctypes.Structure):
         ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("h", ctypes.c_double),
         ("zedge", ctypes.POINTER(ctypes.c_double)),
         ("incl", ctypes.c_double), ("decl", ctypes.c_double), ("scale", ctypes.c_double),
+        ("w", ctypes.c_double * 6),
     ]
 
 
@@ -88,7 +92,7 @@ def _lib():
         ip = ctypes.POINTER(ctypes.c_int32)
         pp = ctypes.POINTER(_Problem)
         L.orc_prism_value.restype = ctypes.c_double
-        L.orc_prism_value.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_double,
+        L.orc_prism_value.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_double, dp,
                                       ctypes.c_double, ctypes.c_int, dp]
         L.orc_dense_G.restype = ctypes.c_int
         L.orc_dense_G.argtypes = [pp, dp]
@@ -136,6 +140,7 @@ class Problem:
     decl: float = 0.0
     field_nT: float = 50000.0
     scale: float = 0.0
+    w: tuple = (0.0, 0.0, 0.0, 0.0, 0.0, 0.0)   # HESSIAN: w_xx, w_yy, w_zz, w_xy, w_xz, w_yz
     _keep: list = field(default_factory=list, repr=False)
 
     @property
@@ -175,25 +180,29 @@ class Problem:
         self._keep[:] = [z]
         return _Problem(self.kind, self.sx, self.sy, self.nz, self.pxl, self.pxr, self.pyl,
                         self.pyr, self.dx, self.dy, self.h, _dptr(z), self.incl, self.decl,
-                        self.effective_scale())
+                        self.effective_scale(), (ctypes.c_double * 6)(*[float(v) for v in self.w]))
 
 
 def problem_from_dict(pr: dict) -> Problem:
     """Problem from a plain description dict (keys as in workloads.problem)."""
-    kind = {"gravity": GRAVITY, "magnetic": MAGNETIC, "probe": PROBE}[pr["kind"]]
+    kind = {"gravity": GRAVITY, "magnetic": MAGNETIC, "probe": PROBE, "hessian": HESSIAN}[pr["kind"]]
+    w = tuple(pr.get("hessian") or (0.0,) * 6)
     return Problem(kind=kind, sx=pr["sx"], sy=pr["sy"], nz=pr["nz"], pxl=pr["pxl"], pxr=pr["pxr"],
                    pyl=pr["pyl"], pyr=pr["pyr"], dx=pr["dx"], dy=pr["dy"], dz=pr["dz"],
                    z_edges=pr["z_edges"], h=pr["h"], incl=pr["incl"], decl=pr["decl"],
-                   field_nT=pr["field_nT"], scale=pr["scale"])
+                   field_nT=pr["field_nT"], scale=pr["scale"], w=w)
 
 
 def prism_value(kind: int, b, incl: float = 90.0, decl: float = 0.0, scale: float = 1.0,
-                quad: bool = False):
+                quad: bool = False, w=None):
     """scale * signed 8-corner sum for one prism b = (chi1, chi2, ups1, ups2, zeta1, zeta2)
-    relative to the station.  Returns (value, sum of |corner terms| * |scale|)."""
+    relative to the station (kind HESSIAN: with the component weights w).
+    Returns (value, sum of |corner terms| * |scale|)."""
     bb = np.ascontiguousarray(b, dtype=np.float64)
+    ww = np.ascontiguousarray(w if w is not None else np.zeros(6), dtype=np.float64)
+    assert ww.shape == (6,)
     a = ctypes.c_double(0.0)
-    v = _lib().orc_prism_value(kind, _dptr(bb), incl, decl, scale, int(quad), ctypes.byref(a))
+    v = _lib().orc_prism_value(kind, _dptr(bb), incl, decl, _dptr(ww), scale, int(quad), ctypes.byref(a))
     return v, a.value
 
 

@@ -19,7 +19,10 @@
  *
  * kind: 0 = gravity g_z (Sec. 4.1), 1 = magnetic total-field anomaly for
  * induced magnetisation (Sec. 4.2), 2 = an index probe whose entry is
- * (p - pxl - i) + 4096 (q - pyl - j) + 2^24 r, computed from the geometry.
+ * (p - pxl - i) + 4096 (q - pyl - j) + 2^24 r, computed from the geometry,
+ * 3 = sum_ab w_ab U_ab, a weighted sum of the second derivatives of the
+ * prism's potential with respect to the station, each component from its own
+ * closed form (a user-chosen kernel, Sec. 1 (vi)).
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC ... -lquadmath -lm
  * (no fast-math: IEEE round-to-nearest throughout).
@@ -72,7 +75,23 @@ typedef struct {
     const double *zedge;          /* nz + 1 increasing depths [m]            */
     double incl, decl;            /* magnetic field direction [deg]          */
     double scale;                 /* gamma (gravity) or F / (4 pi) (magnetic) */
+    double w[6];                  /* kind 3: w_xx, w_yy, w_zz, w_xy, w_xz, w_yz */
 } orc_problem;
+
+/* the weights orc_prism takes for a problem: magnetic G_1..G_5 (kind 1), the
+ * component weights (kind 3), zeros otherwise */
+static void orc_weights_d(const orc_problem *P, double g[6])
+{
+    for (int t = 0; t < 6; ++t) g[t] = 0;
+    if (P->kind == 1) orc_mag_weights_d(P->incl, P->decl, g);
+    if (P->kind == 3) for (int t = 0; t < 6; ++t) g[t] = P->w[t];
+}
+static void orc_weights_q(const orc_problem *P, __float128 g[6])
+{
+    for (int t = 0; t < 6; ++t) g[t] = 0;
+    if (P->kind == 1) orc_mag_weights_q(P->incl, P->decl, g);
+    if (P->kind == 3) for (int t = 0; t < 6; ++t) g[t] = P->w[t];
+}
 
 static int orc_nx(const orc_problem *P) { return P->sx + P->pxl + P->pxr; }
 static int orc_ny(const orc_problem *P) { return P->sy + P->pyl + P->pyr; }
@@ -99,7 +118,7 @@ static double orc_probe_value(const orc_problem *P, const double b[6], int r)
     return ox + 4096.0 * oy + 16777216.0 * r;
 }
 
-static double orc_entry_d(const orc_problem *P, const double g[5], int i, int j, int p, int q, int r,
+static double orc_entry_d(const orc_problem *P, const double g[6], int i, int j, int p, int q, int r,
                           double *abs_sum)
 {
     double b[6];
@@ -111,7 +130,7 @@ static double orc_entry_d(const orc_problem *P, const double g[5], int i, int j,
     return P->scale * v;
 }
 
-static double orc_entry_q(const orc_problem *P, const __float128 g[5], int i, int j, int p, int q,
+static double orc_entry_q(const orc_problem *P, const __float128 g[6], int i, int j, int p, int q,
                           int r, double *abs_sum)
 {
     double bd[6];
@@ -141,20 +160,22 @@ static double orc_entry_q(const orc_problem *P, const __float128 g[5], int i, in
 /* One arbitrary prism, b = {chi1, chi2, ups1, ups2, zeta1, zeta2} relative to
  * the station; returns scale * (signed corner sum).  quad != 0 evaluates in
  * __float128 and rounds once.  Used by the pins on the closed forms. */
-double orc_prism_value(int kind, const double *b, double incl, double decl, double scale,
+double orc_prism_value(int kind, const double *b, double incl, double decl, const double *w6, double scale,
                        int quad, double *abs_sum)
 {
     double a = 0;
     if (quad) {
-        __float128 bq[6], gq[5] = {0, 0, 0, 0, 0}, aq = 0;
+        __float128 bq[6], gq[6] = {0, 0, 0, 0, 0, 0}, aq = 0;
         for (int t = 0; t < 6; ++t) bq[t] = b[t];
         if (kind == 1) orc_mag_weights_q(incl, decl, gq);
+        if (kind == 3) for (int t = 0; t < 6; ++t) gq[t] = w6[t];
         __float128 v = orc_prism_q(kind, bq, gq, &aq);
         if (abs_sum) *abs_sum = (double)(fabsq((__float128)scale) * aq);
         return (double)((__float128)scale * v);
     }
-    double g[5] = {0, 0, 0, 0, 0};
+    double g[6] = {0, 0, 0, 0, 0, 0};
     if (kind == 1) orc_mag_weights_d(incl, decl, g);
+    if (kind == 3) for (int t = 0; t < 6; ++t) g[t] = w6[t];
     double v = orc_prism_d(kind, b, g, &a);
     if (abs_sum) *abs_sum = fabs(scale) * a;
     return scale * v;
@@ -165,8 +186,8 @@ int orc_dense_G(const orc_problem *P, double *G)
 {
     const int nx = orc_nx(P), ny = orc_ny(P);
     const int64_t n = (int64_t)nx * ny * P->nz;
-    double g[5] = {0, 0, 0, 0, 0};
-    if (P->kind == 1) orc_mag_weights_d(P->incl, P->decl, g);
+    double g[6];
+    orc_weights_d(P, g);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int k = 0; k < P->sx * P->sy; ++k) {
         const int i = k % P->sx, j = k / P->sx;
@@ -184,12 +205,12 @@ int orc_dense_G(const orc_problem *P, double *G)
 double orc_entry(const orc_problem *P, int i, int j, int p, int q, int r, int quad, double *abs_sum)
 {
     if (quad) {
-        __float128 g[5] = {0, 0, 0, 0, 0};
-        if (P->kind == 1) orc_mag_weights_q(P->incl, P->decl, g);
+        __float128 g[6];
+        orc_weights_q(P, g);
         return orc_entry_q(P, g, i, j, p, q, r, abs_sum);
     }
-    double g[5] = {0, 0, 0, 0, 0};
-    if (P->kind == 1) orc_mag_weights_d(P->incl, P->decl, g);
+    double g[6];
+    orc_weights_d(P, g);
     return orc_entry_d(P, g, i, j, p, q, r, abs_sum);
 }
 
@@ -206,8 +227,8 @@ int orc_offset_table_quad(const orc_problem *P, double *table, double *abs_table
 {
     const int nx = orc_nx(P), ny = orc_ny(P);
     const int wx = P->sx + nx - 1, wy = P->sy + ny - 1;
-    __float128 g[5] = {0, 0, 0, 0, 0};
-    if (P->kind == 1) orc_mag_weights_q(P->incl, P->decl, g);
+    __float128 g[6];
+    orc_weights_q(P, g);
     const int64_t per = (int64_t)wx * wy;
 #pragma omp parallel for collapse(2) schedule(dynamic, 4)
     for (int r = 0; r < P->nz; ++r)
@@ -239,8 +260,8 @@ int orc_offset_table_quad(const orc_problem *P, double *table, double *abs_table
 int orc_station_sums(const orc_problem *P, const double *m, int ns, const int32_t *ij, double *out)
 {
     const int nx = orc_nx(P), ny = orc_ny(P);
-    double g[5] = {0, 0, 0, 0, 0};
-    if (P->kind == 1) orc_mag_weights_d(P->incl, P->decl, g);
+    double g[6];
+    orc_weights_d(P, g);
     const int64_t ce = (int64_t)(nx + 1) * (ny + 1);
     double *lo = (double *)malloc(sizeof(double) * ce);
     double *hi = (double *)malloc(sizeof(double) * ce);
@@ -268,9 +289,7 @@ int orc_station_sums(const orc_problem *P, const double *m, int ns, const int32_
                     const double ups = (f - P->pyl) * P->dy - bb;
                     for (int e = 0; e <= nx; ++e) {
                         const double chi = (e - P->pxl) * P->dx - a;
-                        dst[(int64_t)f * (nx + 1) + e] = (P->kind == 0)
-                            ? orc_grav_corner_d(chi, ups, zeta)
-                            : orc_mag_corner_d(chi, ups, zeta, g);
+                        dst[(int64_t)f * (nx + 1) + e] = orc_corner_d(P->kind, chi, ups, zeta, g);
                     }
                 }
             }
@@ -304,8 +323,8 @@ int orc_station_sums(const orc_problem *P, const double *m, int ns, const int32_
  */
 int orc_prism_sums(const orc_problem *P, const double *v, int np, const int32_t *pqr, double *out)
 {
-    double g[5] = {0, 0, 0, 0, 0};
-    if (P->kind == 1) orc_mag_weights_d(P->incl, P->decl, g);
+    double g[6];
+    orc_weights_d(P, g);
     for (int s = 0; s < np; ++s) {
         const int p = pqr[3 * s], q = pqr[3 * s + 1], r = pqr[3 * s + 2];
         long double acc = 0;
@@ -332,8 +351,8 @@ int orc_station_sums_quad(const orc_problem *P, const double *m, int ns, const i
 {
     const int nx = orc_nx(P), ny = orc_ny(P);
     if (P->kind == 2) return 2;
-    __float128 g[5] = {0, 0, 0, 0, 0};
-    if (P->kind == 1) orc_mag_weights_q(P->incl, P->decl, g);
+    __float128 g[6];
+    orc_weights_q(P, g);
     const int64_t ce = (int64_t)(nx + 1) * (ny + 1);
     __float128 *lo = (__float128 *)malloc(sizeof(__float128) * ce);
     __float128 *hi = (__float128 *)malloc(sizeof(__float128) * ce);
@@ -354,9 +373,7 @@ int orc_station_sums_quad(const orc_problem *P, const double *m, int ns, const i
                     const __float128 ups = (__float128)(f - P->pyl) * P->dy - bb;
                     for (int e = 0; e <= nx; ++e) {
                         const __float128 chi = (__float128)(e - P->pxl) * P->dx - a;
-                        dst[(int64_t)f * (nx + 1) + e] = (P->kind == 0)
-                            ? orc_grav_corner_q(chi, ups, zeta)
-                            : orc_mag_corner_q(chi, ups, zeta, g);
+                        dst[(int64_t)f * (nx + 1) + e] = orc_corner_q(P->kind, chi, ups, zeta, g);
                     }
                 }
             }
@@ -385,8 +402,8 @@ int orc_station_sums_quad(const orc_problem *P, const double *m, int ns, const i
 int orc_prism_sums_quad(const orc_problem *P, const double *v, int np, const int32_t *pqr, double *out)
 {
     if (P->kind == 2) return 2;
-    __float128 g[5] = {0, 0, 0, 0, 0};
-    if (P->kind == 1) orc_mag_weights_q(P->incl, P->decl, g);
+    __float128 g[6];
+    orc_weights_q(P, g);
     __float128 *part = (__float128 *)malloc(sizeof(__float128) * P->sy);
     if (!part) return 1;
     for (int s = 0; s < np; ++s) {

@@ -12,7 +12,7 @@ BTTB_OK = 0
 STATUS_NAMES = {0: "BTTB_OK", 1: "BTTB_ERR_INVALID_VALUE", 2: "BTTB_ERR_NULL_POINTER",
                 3: "BTTB_ERR_UNSUPPORTED", 4: "BTTB_ERR_WORKSPACE_TOO_SMALL", 5: "BTTB_ERR_HIP",
                 6: "BTTB_ERR_INTERNAL"}
-BTTB_GRAVITY_GZ, BTTB_MAGNETIC_TMI, BTTB_USER_TABLE, BTTB_PROBE = 0, 1, 2, 99
+BTTB_GRAVITY_GZ, BTTB_MAGNETIC_TMI, BTTB_USER_TABLE, BTTB_HESSIAN, BTTB_PROBE = 0, 1, 2, 3, 99
 BTTB_FP32, BTTB_FP64 = 0, 1
 BTTB_ACC_DEFAULT, BTTB_ACC_PLAIN, BTTB_ACC_TWOSUM, BTTB_ACC_WIDE = 0, 1, 2, 3
 BTTB_SPECTRUM_AUTO, BTTB_SPECTRUM_COMPLEX, BTTB_SPECTRUM_REAL_EVEN = 0, 1, 2
@@ -47,6 +47,7 @@ class ProblemDesc(ctypes.Structure):
         ("accumulation", ctypes.c_int32), ("layer_chunk", ctypes.c_int32),
         ("row_tile", ctypes.c_int32), ("col_tile", ctypes.c_int32),
         ("spectrum_form", ctypes.c_int32),
+        ("hessian", ctypes.c_double * 6),
     ]
 
 

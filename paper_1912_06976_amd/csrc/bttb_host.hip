@@ -89,12 +89,18 @@ struct bttb_plan_s {
 
 namespace {
 
+// a BTTB_HESSIAN kernel without off-diagonal weights: even in both offsets
+bool hessian_even(const bttb_problem_desc* d)
+{
+    return d->problem == BTTB_HESSIAN && d->hessian[3] == 0.0 && d->hessian[4] == 0.0 && d->hessian[5] == 0.0;
+}
+
 bttb_status validate_and_fill(const bttb_problem_desc* d, bttb_plan_s* P)
 {
     if (d->problem != BTTB_GRAVITY_GZ && d->problem != BTTB_MAGNETIC_TMI && d->problem != BTTB_USER_TABLE &&
-        d->problem != BTTB_PROBE)
+        d->problem != BTTB_HESSIAN && d->problem != BTTB_PROBE)
         return fail(BTTB_ERR_INVALID_VALUE,
-                    "problem must be BTTB_GRAVITY_GZ, BTTB_MAGNETIC_TMI, BTTB_USER_TABLE or BTTB_PROBE");
+                    "problem must be BTTB_GRAVITY_GZ, BTTB_MAGNETIC_TMI, BTTB_USER_TABLE, BTTB_HESSIAN or BTTB_PROBE");
     if (d->precision != BTTB_FP32 && d->precision != BTTB_FP64)
         return fail(BTTB_ERR_INVALID_VALUE, "precision must be BTTB_FP32 or BTTB_FP64");
     if (d->sx < 1 || d->sy < 1 || d->nz < 1)
@@ -124,6 +130,9 @@ bttb_status validate_and_fill(const bttb_problem_desc* d, bttb_plan_s* P)
         for (int r = 0; r <= d->nz; ++r) P->z[r] = r * d->dz;
     }
     if (!std::isfinite(d->scale)) return fail(BTTB_ERR_INVALID_VALUE, "scale must be finite");
+    if (d->problem == BTTB_HESSIAN)
+        for (int k = 0; k < 6; ++k)
+            if (!std::isfinite(d->hessian[k])) return fail(BTTB_ERR_INVALID_VALUE, "hessian weights must be finite");
     if (d->problem == BTTB_MAGNETIC_TMI) {
         if (!std::isfinite(d->inclination_deg) || d->inclination_deg < -90.0 || d->inclination_deg > 90.0)
             return fail(BTTB_ERR_INVALID_VALUE, "inclination_deg must be in [-90, 90]");
@@ -151,8 +160,9 @@ bttb_status validate_and_fill(const bttb_problem_desc* d, bttb_plan_s* P)
     // smallest that also holds the centred even generator,
     // N >= 2 (s - 1 + max(p_L, p_R)) + 1, so that its four times smaller
     // spectra apply
-    const bool want_even = (d->problem == BTTB_GRAVITY_GZ && d->spectrum_form == BTTB_SPECTRUM_AUTO) ||
-                           d->spectrum_form == BTTB_SPECTRUM_REAL_EVEN;
+    const bool want_even =
+        ((d->problem == BTTB_GRAVITY_GZ || hessian_even(d)) && d->spectrum_form == BTTB_SPECTRUM_AUTO) ||
+        d->spectrum_form == BTTB_SPECTRUM_REAL_EVEN;
     const int64_t evx = 2 * ((int64_t)d->sx - 1 + std::max(d->pxl, d->pxr)) + 1;
     const int64_t evy = 2 * ((int64_t)d->sy - 1 + std::max(d->pyl, d->pyr)) + 1;
     auto pick = [](int64_t lo, int64_t even_lo) {
@@ -193,6 +203,17 @@ bttb_status validate_and_fill(const bttb_problem_desc* d, bttb_plan_s* P)
     P->w.g[2] = 2 * L * M;
     P->w.g[3] = N * N - M * M;
     P->w.g[4] = N * N - L * L;
+    if (d->problem == BTTB_HESSIAN) {
+        // the same five corner terms for any weights: sum w_ab U_ab with
+        // U_zz = -U_xx - U_yy is w_yz U_yz + w_xz U_xz + w_xy U_xy
+        // + (w_zz - w_yy)(-U_yy) + (w_zz - w_xx)(-U_xx)
+        const double* w = d->hessian;
+        P->w.g[0] = w[5];
+        P->w.g[1] = w[4];
+        P->w.g[2] = w[3];
+        P->w.g[3] = w[2] - w[1];
+        P->w.g[4] = w[2] - w[0];
+    }
     if (d->scale != 0.0) P->scale = d->scale;
     else if (d->problem == BTTB_GRAVITY_GZ) P->scale = 6.6743e-11 * 1e3 * 1e5;  // mGal per (g/cm^3 m)
     else if (d->problem == BTTB_MAGNETIC_TMI) P->scale = d->field_nT / (4.0 * M_PI);
@@ -215,13 +236,15 @@ bttb_status validate_and_fill(const bttb_problem_desc* d, bttb_plan_s* P)
     P->bx = d->sx - 1 + std::max(d->pxl, d->pxr);
     P->by = d->sy - 1 + std::max(d->pyl, d->pyr);
     const bool fits = 2 * (int64_t)P->bx + 1 <= Nx && 2 * (int64_t)P->by + 1 <= Ny;
-    const bool even_ok = (d->problem == BTTB_GRAVITY_GZ || d->problem == BTTB_USER_TABLE) && fits;
+    const bool even_ok = (d->problem == BTTB_GRAVITY_GZ || d->problem == BTTB_USER_TABLE || hessian_even(d)) && fits;
     if (d->spectrum_form == BTTB_SPECTRUM_REAL_EVEN && !even_ok)
         return fail(BTTB_ERR_UNSUPPORTED,
-                    "BTTB_SPECTRUM_REAL_EVEN needs the gravity kernel (or an even user table) and "
-                    "nx_fft >= 2 (sx - 1 + max(pxl, pxr)) + 1, ny_fft >= 2 (sy - 1 + max(pyl, pyr)) + 1");
+                    "BTTB_SPECTRUM_REAL_EVEN needs the gravity kernel, a BTTB_HESSIAN kernel with zero off-diagonal "
+                    "weights (or an even user table) and nx_fft >= 2 (sx - 1 + max(pxl, pxr)) + 1, "
+                    "ny_fft >= 2 (sy - 1 + max(pyl, pyr)) + 1");
     const bool use_even = d->spectrum_form == BTTB_SPECTRUM_REAL_EVEN ||
-                          (d->spectrum_form == BTTB_SPECTRUM_AUTO && d->problem == BTTB_GRAVITY_GZ && fits);
+                          (d->spectrum_form == BTTB_SPECTRUM_AUTO &&
+                           (d->problem == BTTB_GRAVITY_GZ || hessian_even(d)) && fits);
     P->form = use_even ? FORM_REAL_EVEN : FORM_COMPLEX;
     // corner grid: the entries' offsets are [-(sx - 1 + pxl), nx - 1 - pxl]
     // (centred placement: [0, bx]); one more corner than entries per axis
@@ -314,7 +337,7 @@ GenParams gen_params(const bttb_plan_s* P, int r0, int nl, const double* table =
     g.cx = P->cx;
     g.cy = P->cy;
     g.kind = P->d.problem == BTTB_GRAVITY_GZ ? KIND_GRAVITY
-           : P->d.problem == BTTB_MAGNETIC_TMI ? KIND_MAGNETIC
+           : P->d.problem == BTTB_MAGNETIC_TMI || P->d.problem == BTTB_HESSIAN ? KIND_MAGNETIC
            : P->d.problem == BTTB_USER_TABLE ? KIND_TABLE : KIND_PROBE;
     g.table = table;
     g.wx = P->sx + P->nx - 1;
@@ -347,7 +370,8 @@ bttb_status run_generate(const bttb_plan_s* P, char* spec, char* ws, hipStream_t
     double* g64 = (double*)(ws + L.gen_a);
     double2* w64 = (double2*)(ws + L.gen_b);
     double* corners = (double*)(ws + L.gen_c);
-    const bool closed_form = P->d.problem == BTTB_GRAVITY_GZ || P->d.problem == BTTB_MAGNETIC_TMI;
+    const bool closed_form =
+        P->d.problem == BTTB_GRAVITY_GZ || P->d.problem == BTTB_MAGNETIC_TMI || P->d.problem == BTTB_HESSIAN;
     void* out = spec + P->off_spec;
     const double inv = 1.0 / ((double)P->Nx * (double)P->Ny);
     for (int r0 = 0; r0 < P->nz; r0 += P->gen_batch) {
@@ -1060,7 +1084,8 @@ bttb_status bttb_debug_generator(bttb_plan_t plan, int32_t layer, double* host_o
         double* corners = (double*)((char*)workspace + ws_layout(plan, 1).gen_c);
         const GenParams g = gen_params(plan, layer, 1, nullptr, corners);
         bttb_status st = BTTB_OK;
-        if (plan->d.problem == BTTB_GRAVITY_GZ || plan->d.problem == BTTB_MAGNETIC_TMI)
+        if (plan->d.problem == BTTB_GRAVITY_GZ || plan->d.problem == BTTB_MAGNETIC_TMI ||
+            plan->d.problem == BTTB_HESSIAN)
             st = hip_check(launch_corners(g, 1, corners, s), "corners");
         if (st == BTTB_OK) st = hip_check(launch_generate(g, layer, 1, (double*)workspace, s), "generate");
         if (st != BTTB_OK) return st;

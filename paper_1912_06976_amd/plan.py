@@ -17,7 +17,7 @@ from . import _lib
 from ._lib import check
 
 _KIND = {"gravity": _lib.BTTB_GRAVITY_GZ, "magnetic": _lib.BTTB_MAGNETIC_TMI, "table": _lib.BTTB_USER_TABLE,
-         "probe": _lib.BTTB_PROBE}
+         "hessian": _lib.BTTB_HESSIAN, "probe": _lib.BTTB_PROBE}
 _PREC = {"fp32": _lib.BTTB_FP32, "fp64": _lib.BTTB_FP64}
 _FORM = {"auto": _lib.BTTB_SPECTRUM_AUTO, "complex": _lib.BTTB_SPECTRUM_COMPLEX,
          "real_even": _lib.BTTB_SPECTRUM_REAL_EVEN}
@@ -58,8 +58,32 @@ def make_desc(problem: dict, precision: str = "fp32", accumulation: str = "defau
         nx_fft=problem.get("nx_fft", 0), ny_fft=problem.get("ny_fft", 0),
         accumulation=_ACC[accumulation], layer_chunk=problem.get("layer_chunk", 0),
         row_tile=problem.get("row_tile", 0), col_tile=problem.get("col_tile", 0),
-        spectrum_form=_FORM[problem.get("spectrum_form", "auto")])
+        spectrum_form=_FORM[problem.get("spectrum_form", "auto")],
+        hessian=(ctypes.c_double * 6)(*[float(v) for v in (problem.get("hessian") or (0.0,) * 6)]))
     return d, keep
+
+
+def _unit(incl_deg: float, decl_deg: float):
+    i, d = math.radians(incl_deg), math.radians(decl_deg)
+    return (math.cos(i) * math.cos(d), math.cos(i) * math.sin(d), math.sin(i))
+
+
+def hessian_weights_tmi(incl: float, decl: float, m_incl: float, m_decl: float):
+    """Weights (w_xx, w_yy, w_zz, w_xy, w_xz, w_yz) of a "hessian" kernel for
+    the total-field anomaly f^T U m of a magnetisation of direction (m_incl,
+    m_decl) in a field of direction (incl, decl) (x North, y East, z down):
+    w_aa = f_a m_a, w_ab = f_a m_b + f_b m_a."""
+    f, m = _unit(incl, decl), _unit(m_incl, m_decl)
+    return (f[0] * m[0], f[1] * m[1], f[2] * m[2], f[0] * m[1] + f[1] * m[0],
+            f[0] * m[2] + f[2] * m[0], f[1] * m[2] + f[2] * m[1])
+
+
+def hessian_weights_component(a: str, b: str):
+    """Weights selecting one component U_ab (a, b in "xyz"), e.g. ("z", "z")
+    for the gravity gradient g_zz."""
+    key = "".join(sorted(a + b))
+    order = ["xx", "yy", "zz", "xy", "xz", "yz"]
+    return tuple(1.0 if k == key else 0.0 for k in order)
 
 
 def bttb_plan_create(problem: dict, precision: str = "fp32", accumulation: str = "default") -> int:

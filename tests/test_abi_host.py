@@ -56,7 +56,7 @@ def _create(prob, prec="fp32", **over):
 
 @pytest.mark.parametrize("field,value,status", [
     ("sx", 0, 1), ("sy", -3, 1), ("nz", 0, 1), ("pxl", -1, 1), ("dx", 0.0, 1), ("dy", float("nan"), 1),
-    ("dz", -1.0, 1), ("station_height", -1.0, 1), ("problem", 7, 1), ("problem", 3, 1), ("precision", 3, 1),
+    ("dz", -1.0, 1), ("station_height", -1.0, 1), ("problem", 7, 1), ("problem", 4, 1), ("precision", 3, 1),
     ("nx", 17, 1), ("nx_fft", 16, 1), ("nx_fft", 100, 3), ("nx_fft", 432, 3), ("ny_fft", 8192, 3), ("accumulation", 9, 1),
     ("layer_chunk", -1, 1), ("row_tile", 3, 1), ("col_tile", 4, 1), ("spectrum_form", 3, 1),
 ])
@@ -262,3 +262,18 @@ def test_noalloc_scratch_size_matches_header():
     from paper_1912_06976_amd import _lib
     m = re.search(r"#define BTTB_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", txt)
     assert m and int(m.group(1)) << int(m.group(2)) == _lib.NOALLOC_SCRATCH_BYTES
+
+
+def test_hessian_descriptor_checks(lib):
+    import paper_1912_06976_amd as B
+    base = W.problem(W.HESSIAN, 12, 10, 3, 1, 2, 0, 1, dx=50.0, dy=50.0, dz=25.0, hessian=(0, 0, 1, 0, 0, 0))
+    st, _, msg = _create(dict(base, hessian=(0, 0, float("nan"), 0, 0, 0)))
+    assert st == 1 and "hessian" in msg
+    # off-diagonal weights make the kernel odd in an offset: no real even form
+    st, _, msg = _create(dict(base, hessian=(0, 0, 1, 0, 0.5, 0), spectrum_form="real_even"))
+    assert st == 3 and "REAL_EVEN" in msg
+    for w, form in (((0, 0, 1, 0, 0, 0), "real_even"), ((1, -1, 0, 0, 0, 0), "real_even"),
+                    ((0, 0, 1, 0.2, 0, 0), "complex")):
+        h = B.bttb_plan_create(dict(base, hessian=w), "fp32")
+        assert B.bttb_plan_spectrum_form(h) == form, w
+        B.bttb_plan_destroy(h)

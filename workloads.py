@@ -24,18 +24,20 @@ import math
 
 import numpy as np
 
-GRAVITY, MAGNETIC, TABLE, PROBE = "gravity", "magnetic", "table", "probe"
+GRAVITY, MAGNETIC, TABLE, HESSIAN, PROBE = "gravity", "magnetic", "table", "hessian", "probe"
 
 
 def problem(kind, sx, sy, nz, pxl=0, pxr=0, pyl=0, pyr=0, dx=1.0, dy=1.0, dz=1.0,
             z_edges=None, h=0.0, incl=90.0, decl=0.0, field_nT=50000.0, scale=0.0,
-            nx_fft=0, ny_fft=0):
-    """A plain dict describing one problem (the parameter set of Table 2)."""
+            nx_fft=0, ny_fft=0, hessian=None):
+    """A plain dict describing one problem (the parameter set of Table 2;
+    hessian: the six weights of a "hessian" kernel)."""
     return dict(kind=kind, sx=int(sx), sy=int(sy), nz=int(nz), pxl=int(pxl), pxr=int(pxr),
                 pyl=int(pyl), pyr=int(pyr), dx=float(dx), dy=float(dy), dz=float(dz),
                 z_edges=None if z_edges is None else np.asarray(z_edges, dtype=np.float64),
                 h=float(h), incl=float(incl), decl=float(decl), field_nT=float(field_nT),
-                scale=float(scale), nx_fft=int(nx_fft), ny_fft=int(ny_fft))
+                scale=float(scale), nx_fft=int(nx_fft), ny_fft=int(ny_fft),
+                hessian=None if hessian is None else tuple(float(v) for v in hessian))
 
 
 def dims(pr):
