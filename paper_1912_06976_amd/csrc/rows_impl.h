@@ -23,6 +23,16 @@ template <int N> __device__ __forceinline__ int mirror_pos(int k)
     if constexpr (FftShape<N>::POW2) return (N - k) & (N - 1);
     else return k == 0 || k == N ? 0 : N - k;
 }
+// Row length of an LDS staging tile of k rows whose accesses by a
+// wavefront touch k rows at a few consecutive columns: the smallest
+// length >= n congruent to 32 / k modulo 32, so that those elements sit in
+// distinct 8-byte bank pairs (for many rows or short ones: an odd length).
+constexpr int spread_len(int n, int k)
+{
+    if (k >= 32 || n < 32) return n % 2 ? n : n + 1;
+    const int r = 32 / k;
+    return n + ((r - n) % 32 + 32) % 32;
+}
 // P0: pairs of rows per block for long rows (a tuning choice, 2 or 4)
 template <typename T, int N, int P0 = 4> struct RowCfg {
     static constexpr int TPL = FftShape<N>::TPL;
@@ -33,18 +43,24 @@ template <typename T, int N, int P0 = 4> struct RowCfg {
     static constexpr int RT = 2 * PAIRS;            // rows per block
     static constexpr int THREADS = PAIRS * TPL;
     static constexpr int HALF = N / 2;              // packed half-spectrum columns
-    static constexpr int SROW = RT + 1;             // padded staging row
-    static constexpr int STAGE = HALF * SROW;
     static constexpr int XCH = PAIRS * lds_line_elems(N);
-    static constexpr int LDS = STAGE > XCH ? STAGE : XCH;
+    // c2r: the tile of packed half spectra staged [row][kx], row length CR:
+    // the tile's loads (RT rows of a few kx per wavefront) and the line
+    // reads (consecutive kx of one row) fall on distinct banks
+    static constexpr int CR = spread_len(HALF, RT);
+    static constexpr int CSTAGE = RT * CR;
+    static constexpr int LDS = CSTAGE > XCH ? CSTAGE : XCH;
     static constexpr int TWO = LDS;                 // offset of the LDS twiddle table
-    // r2c: the complex transforms Z of the PAIRS row pairs staged by
-    // frequency, [k][pair] with a padded row (bank spread of the writes)
-    // (FP32 only; FP64 splits through the line buffers and stages the half
-    // spectra [kx][row] like the c2r tile, which measured faster there)
-    static constexpr int ZROW = PAIRS > 1 ? PAIRS + 1 : 1;
-    static constexpr int ZSTAGE = N * ZROW;
-    static constexpr int LDS_R2C = sizeof(T) == 4 ? (ZSTAGE > XCH ? ZSTAGE : XCH) : LDS;
+    // r2c (FP32): the complex transforms Z of the PAIRS row pairs staged
+    // [pair][k], row length ZR (the writes of a line are consecutive, the
+    // split's reads take PAIRS pairs of a few k)
+    static constexpr int ZR = spread_len(N, PAIRS);
+    static constexpr int ZSTAGE = PAIRS * ZR;
+    // r2c (FP64): the half spectra of the RT rows staged [kx][row] (split
+    // through the line buffers first, which measured faster there)
+    static constexpr int SROW = RT + 1;
+    static constexpr int STAGE = HALF * SROW;
+    static constexpr int LDS_R2C = sizeof(T) == 4 ? (ZSTAGE > XCH ? ZSTAGE : XCH) : (STAGE > XCH ? STAGE : XCH);
 };
 
 // Row kernels are persistent: gridDim.x blocks (about the number that fit on
@@ -110,20 +126,20 @@ k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
             // both rows (adjacent in the column) with one 16-byte store
             __syncthreads();
 #pragma unroll
-            for (int m = 0; m < P; ++m) lds[(t + m * TPL) * C::ZROW + pr] = v[m];
+            for (int m = 0; m < P; ++m) lds[pr * C::ZR + t + m * TPL] = v[m];
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < (C::HALF * C::PAIRS) / C::THREADS; ++i) {
                 const int e = threadIdx.x + i * C::THREADS;
                 const int kx = e / C::PAIRS, q = e % C::PAIRS;
-                const cT<T> z = lds[kx * C::ZROW + q];
+                const cT<T> z = lds[q * C::ZR + kx];
                 cT<T> A, Cc;
                 if (kx == 0) {
-                    const cT<T> zh = lds[(N / 2) * C::ZROW + q];
+                    const cT<T> zh = lds[q * C::ZR + N / 2];
                     A = mk<T>(z.x, zh.x);
                     Cc = mk<T>(z.y, zh.y);
                 } else {
-                    const cT<T> zr = lds[(N - kx) * C::ZROW + q];
+                    const cT<T> zr = lds[q * C::ZR + N - kx];
                     A = mk<T>((T)0.5 * (z.x + zr.x), (T)0.5 * (z.y - zr.y));
                     Cc = mk<T>((T)0.5 * (z.y + zr.y), (T)0.5 * (zr.x - z.x));
                 }
@@ -220,7 +236,7 @@ k_rows_c2r(RowJobs jobs, const cT<T>* __restrict__ tw)
 #pragma unroll
         for (int i = 0; i < P; ++i) {
             const int e = threadIdx.x + i * C::THREADS;
-            lds[(e / C::RT) * C::SROW + e % C::RT] = tl[i];
+            lds[(e % C::RT) * C::CR + e / C::RT] = tl[i];
         }
         __syncthreads();
         if (g + G < total) load(g + G, tl);
@@ -233,12 +249,12 @@ k_rows_c2r(RowJobs jobs, const cT<T>* __restrict__ tw)
             const int kk = k <= N / 2 ? k : N - k;
             cT<T> A, Cc;
             if (kk == 0 || kk == N / 2) {
-                const cT<T> pa = lds[2 * pr], pc = lds[2 * pr + 1];
+                const cT<T> pa = lds[(2 * pr) * C::CR], pc = lds[(2 * pr + 1) * C::CR];
                 A = mk<T>(kk == 0 ? pa.x : pa.y, 0);
                 Cc = mk<T>(kk == 0 ? pc.x : pc.y, 0);
             } else {
-                A = lds[kk * C::SROW + 2 * pr];
-                Cc = lds[kk * C::SROW + 2 * pr + 1];
+                A = lds[(2 * pr) * C::CR + kk];
+                Cc = lds[(2 * pr + 1) * C::CR + kk];
                 if (k > N / 2) { A.y = -A.y; Cc.y = -Cc.y; }
             }
             v[m] = mk<T>(A.x - Cc.y, A.y + Cc.x);

@@ -83,3 +83,49 @@ def test_full_size_sampled(torch_cuda, name):
         gt = np.array([t[rr, q, p] for (p, q, rr) in pq])
         assert _rel(gd, ds) <= tol, (prec, _rel(gd, ds))
         assert _rel(gt, ts) <= tol, (prec, _rel(gt, ts))
+
+
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize_quad_%s.txt" % name)
+    st, sv, pq, pv = [], [], [], []
+    for line in open(path):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if f[0] == "station":
+            st.append((int(f[1]), int(f[2])))
+            sv.append(float(f[3]))
+        else:
+            pq.append((int(f[1]), int(f[2]), int(f[3])))
+            pv.append(float(f[4]))
+    return st, np.array(sv), pq, np.array(pv)
+
+
+@pytest.mark.parametrize("name", ["gravity_1024", "magnetic_288"])
+def test_full_size_against_exact_sums(torch_cuda, name):
+    # The exact sampled products (every corner term and sum in __float128,
+    # tests/golden/fullsize_quad_*.txt, written by make_fullsize_quad.py from
+    # the oracle only).  FP64: within 10x the error of the oracle's own
+    # plain-FP64 direct sums on the same sample (both evaluate the cancelling
+    # corner sums of distant prisms in FP64; the Sec. 5 error metric), and
+    # 1e-12 where that is larger; FP32: 2e-5.
+    import oracle
+    pr, m, r, st_case, pq_case = W.fullsize_case(name)
+    st, sv, pq, pv = _golden(name)
+    assert st == [tuple(x) for x in st_case] and pq == [tuple(x) for x in pq_case]
+    print("full size exact", name, flush=True)
+    out = _run(torch_cuda, pr, m, r)
+    P = oracle_problem(pr)
+    bar_d = max(1e-12, 10 * _rel(oracle.station_sums(P, m, st), sv))
+    bar_t = max(1e-12, 10 * _rel(oracle.prism_sums(P, r, pq), pv))
+    for prec in out:
+        d, t = out[prec]
+        gd = np.array([d[j, i] for (i, j) in st])
+        gt = np.array([t[rr, q, p] for (p, q, rr) in pq])
+        ed, et = _rel(gd, sv), _rel(gt, pv)
+        print("  %s: forward %.2e (bar %.2e), transpose %.2e (bar %.2e)" % (prec, ed, bar_d, et, bar_t), flush=True)
+        if prec == "fp64":
+            assert ed <= bar_d and et <= bar_t, (ed, bar_d, et, bar_t)
+        else:
+            assert ed <= 2e-5 and et <= 2e-5, (ed, et)
