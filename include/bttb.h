@@ -60,7 +60,8 @@ typedef enum {
     BTTB_ERR_UNSUPPORTED = 3,        /* valid but not supported (e.g. FFT length > 4096) */
     BTTB_ERR_WORKSPACE_TOO_SMALL = 4,/* ws_bytes below what bttb_plan_query reports     */
     BTTB_ERR_HIP = 5,                /* a HIP launch or runtime call failed             */
-    BTTB_ERR_INTERNAL = 6
+    BTTB_ERR_INTERNAL = 6,
+    BTTB_ERR_OUT_OF_MEMORY = 7       /* bttb_plan_memory_check: more than is available  */
 } bttb_status;
 
 typedef enum {
@@ -177,6 +178,20 @@ bttb_status bttb_plan_destroy(bttb_plan_t plan);
  * pointer may be NULL.  Errors: NULL_POINTER (plan), INVALID_VALUE (nrhs < 1). */
 bttb_status bttb_plan_query(bttb_plan_t plan, int32_t nrhs, size_t* spectra_bytes,
                             size_t* workspace_bytes, int32_t* nx_fft, int32_t* ny_fft);
+
+/* Memory guard, to call before allocating a plan's buffers (the paper's
+ * software tests each problem size's memory use at set-up so that a problem
+ * too large for the machine is not attempted; Sec. 6, software package).
+ * need = spectra_bytes + workspace_bytes for nrhs + one product's input and
+ * output for nrhs right-hand sides (m and d), each rounded up to 256 bytes.
+ * available: a budget in bytes chosen by the caller, or 0 for the current
+ * device's free memory (hipMemGetInfo).  *need_bytes and *available_bytes
+ * (the figure compared against) are written when not NULL, also on
+ * OUT_OF_MEMORY.  Allocates nothing.  Errors: NULL_POINTER (plan),
+ * INVALID_VALUE (nrhs < 1), OUT_OF_MEMORY (need > available), HIP (the
+ * device query failed). */
+bttb_status bttb_plan_memory_check(bttb_plan_t plan, int32_t nrhs, size_t available, size_t* need_bytes,
+                                   size_t* available_bytes);
 
 /* The spectrum form the plan uses (BTTB_SPECTRUM_COMPLEX or
  * BTTB_SPECTRUM_REAL_EVEN).  Errors: NULL_POINTER. */

@@ -11,7 +11,7 @@ LIB_PATH = os.environ.get("BTTB_LIB", os.path.join(_HERE, "libbttb.so"))
 BTTB_OK = 0
 STATUS_NAMES = {0: "BTTB_OK", 1: "BTTB_ERR_INVALID_VALUE", 2: "BTTB_ERR_NULL_POINTER",
                 3: "BTTB_ERR_UNSUPPORTED", 4: "BTTB_ERR_WORKSPACE_TOO_SMALL", 5: "BTTB_ERR_HIP",
-                6: "BTTB_ERR_INTERNAL"}
+                6: "BTTB_ERR_INTERNAL", 7: "BTTB_ERR_OUT_OF_MEMORY"}
 BTTB_GRAVITY_GZ, BTTB_MAGNETIC_TMI, BTTB_USER_TABLE, BTTB_HESSIAN, BTTB_PROBE = 0, 1, 2, 3, 99
 BTTB_FP32, BTTB_FP64 = 0, 1
 BTTB_ACC_DEFAULT, BTTB_ACC_PLAIN, BTTB_ACC_TWOSUM, BTTB_ACC_WIDE = 0, 1, 2, 3
@@ -20,7 +20,7 @@ BTTB_SPECTRUM_AUTO, BTTB_SPECTRUM_COMPLEX, BTTB_SPECTRUM_REAL_EVEN = 0, 1, 2
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 #: every symbol include/bttb.h declares
-EXPORTS = ["bttb_plan_create", "bttb_plan_destroy", "bttb_plan_query", "bttb_kernel_generate",
+EXPORTS = ["bttb_plan_create", "bttb_plan_destroy", "bttb_plan_query", "bttb_plan_memory_check", "bttb_kernel_generate",
            "bttb_forward", "bttb_transpose", "bttb_forward_noalloc", "bttb_forward_profiled",
            "bttb_transpose_profiled", "bttb_debug_generator", "bttb_plan_spectrum_form", "bttb_kernel_generate_table", "bttb_cgls_query", "bttb_cgls", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
            "bttb_batch_destroy", "bttb_autotune_query", "bttb_autotune", "bttb_status_string",
@@ -74,6 +74,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     L.bttb_plan_destroy.argtypes = [vp]
     L.bttb_plan_query.argtypes = [vp, i32, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(i32),
                                   ctypes.POINTER(i32)]
+    L.bttb_plan_memory_check.argtypes = [vp, i32, sz, ctypes.POINTER(sz), ctypes.POINTER(sz)]
     L.bttb_kernel_generate.argtypes = [vp, vp, vp, sz, vp]
     L.bttb_forward.argtypes = [vp, vp, vp, vp, i32, vp, sz, vp]
     L.bttb_transpose.argtypes = [vp, vp, vp, vp, i32, vp, sz, vp]
@@ -96,7 +97,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
     L.bttb_status_string.restype = ctypes.c_char_p
     L.bttb_last_error.argtypes = []
     L.bttb_last_error.restype = ctypes.c_char_p
-    for name in ["bttb_plan_create", "bttb_plan_destroy", "bttb_plan_query", "bttb_kernel_generate",
+    for name in ["bttb_plan_create", "bttb_plan_destroy", "bttb_plan_query", "bttb_plan_memory_check",
+                 "bttb_kernel_generate",
                  "bttb_forward", "bttb_transpose", "bttb_forward_noalloc", "bttb_forward_profiled",
                  "bttb_transpose_profiled", "bttb_debug_generator", "bttb_plan_spectrum_form", "bttb_kernel_generate_table", "bttb_cgls_query", "bttb_cgls", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
                  "bttb_batch_destroy", "bttb_autotune_query", "bttb_autotune"]:

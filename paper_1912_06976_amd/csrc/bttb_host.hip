@@ -849,6 +849,32 @@ bttb_status bttb_plan_query(bttb_plan_t plan, int32_t nrhs, size_t* spectra_byte
     return BTTB_OK;
 }
 
+bttb_status bttb_plan_memory_check(bttb_plan_t plan, int32_t nrhs, size_t available, size_t* need_bytes,
+                                   size_t* available_bytes)
+{
+    g_last_error.clear();
+    if (!plan) return fail(BTTB_ERR_NULL_POINTER, "plan must not be NULL");
+    if (nrhs < 1) return fail(BTTB_ERR_INVALID_VALUE, "nrhs must be >= 1");
+    const size_t model = (size_t)plan->nx * plan->ny * plan->nz, data = (size_t)plan->sx * plan->sy;
+    // the spectra, the workspace and one product's input plus output, each
+    // rounded up to the allocator's 256-byte granule
+    const size_t need = align_up(plan->spec_bytes) + align_up(ws_layout(plan, nrhs).total) +
+                        align_up((size_t)nrhs * model * plan->esz) + align_up((size_t)nrhs * data * plan->esz);
+    if (available == 0) {
+        size_t free_b = 0, total_b = 0;
+        bttb_status st = hip_check(hipMemGetInfo(&free_b, &total_b), "device memory query");
+        if (st != BTTB_OK) return st;
+        available = free_b;
+    }
+    if (need_bytes) *need_bytes = need;
+    if (available_bytes) *available_bytes = available;
+    if (need > available)
+        return fail(BTTB_ERR_OUT_OF_MEMORY, "the plan's spectra, workspace, input and output for nrhs right-hand "
+                                            "sides need " + std::to_string(need) + " bytes; " +
+                                            std::to_string(available) + " are available");
+    return BTTB_OK;
+}
+
 bttb_status bttb_kernel_generate(bttb_plan_t plan, void* spectra, void* workspace, size_t ws_bytes, void* stream)
 {
     try {
@@ -1550,6 +1576,7 @@ const char* bttb_status_string(bttb_status s)
     case BTTB_ERR_WORKSPACE_TOO_SMALL: return "BTTB_ERR_WORKSPACE_TOO_SMALL";
     case BTTB_ERR_HIP: return "BTTB_ERR_HIP";
     case BTTB_ERR_INTERNAL: return "BTTB_ERR_INTERNAL";
+    case BTTB_ERR_OUT_OF_MEMORY: return "BTTB_ERR_OUT_OF_MEMORY";
     }
     return "unknown bttb_status";
 }

@@ -109,6 +109,18 @@ def bttb_plan_query(plan: int, nrhs: int = 1):
     return sb.value, wb.value, nx.value, ny.value
 
 
+def bttb_plan_memory_check(plan: int, nrhs: int = 1, available: int = 0):
+    """The memory guard: returns (need_bytes, available_bytes) for the plan's
+    spectra, workspace and one product's input and output with nrhs
+    right-hand sides; available = 0 compares against the current device's
+    free memory.  Raises BttbError (BTTB_ERR_OUT_OF_MEMORY) when they do not fit."""
+    need, avail = ctypes.c_size_t(), ctypes.c_size_t()
+    check("bttb_plan_memory_check",
+          _lib.load().bttb_plan_memory_check(ctypes.c_void_p(plan), nrhs, int(available), ctypes.byref(need),
+                                             ctypes.byref(avail)))
+    return need.value, avail.value
+
+
 def bttb_plan_spectrum_form(plan: int) -> str:
     """The plan's stored spectrum form: "complex" or "real_even"."""
     f = ctypes.c_int32()
@@ -269,6 +281,8 @@ class Plan:
         from the caller's entries, [nz, sy + ny - 1, sx + nx - 1] float64 on
         the device, indexed by the cell offsets."""
         if self.spectra is None:
+            with torch.cuda.device(self.device):
+                bttb_plan_memory_check(self.handle, 1)
             self.spectra = torch.empty(self.spectra_bytes, dtype=torch.uint8, device=self.device)
         if self.problem["kind"] == "table":
             if table is None:

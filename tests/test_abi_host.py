@@ -39,7 +39,8 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_status_strings(lib):
-    for code, name in [(0, "BTTB_OK"), (1, "BTTB_ERR_INVALID_VALUE"), (4, "BTTB_ERR_WORKSPACE_TOO_SMALL")]:
+    for code, name in [(0, "BTTB_OK"), (1, "BTTB_ERR_INVALID_VALUE"), (4, "BTTB_ERR_WORKSPACE_TOO_SMALL"),
+                       (7, "BTTB_ERR_OUT_OF_MEMORY")]:
         assert lib.bttb_status_string(code).decode() == name
 
 
@@ -121,6 +122,40 @@ def test_sizes_and_fft_choice(lib):
     B.bttb_plan_destroy(h)
     h = B.bttb_plan_create(dict(W.small_gravity(), nx_fft=64, ny_fft=128), "fp64")
     assert B.bttb_plan_query(h, 1)[2:] == (64, 128)
+    B.bttb_plan_destroy(h)
+
+
+def test_memory_guard_against_a_budget(lib):
+    """The memory check with a caller's budget (no device query): the need is
+    spectra + workspace + one input and output, each rounded to 256 bytes;
+    a budget one byte short is refused with OUT_OF_MEMORY, the exact budget
+    passes, and both figures come back either way."""
+    import paper_1912_06976_amd as B
+    from paper_1912_06976_amd import _lib
+    up = lambda b: (b + 255) // 256 * 256
+    for prob, prec, nrhs in [(W.gravity_1024(), "fp32", 1), (W.magnetic_48x56(), "fp64", 3)]:
+        h = B.bttb_plan_create(prob, prec)
+        sb, wb, _, _ = B.bttb_plan_query(h, nrhs)
+        esz = 4 if prec == "fp32" else 8
+        nx, ny, nz = W.dims(prob)
+        want = up(sb) + up(wb) + up(nrhs * nx * ny * nz * esz) + up(nrhs * prob["sx"] * prob["sy"] * esz)
+        need, avail = B.bttb_plan_memory_check(h, nrhs, want)
+        assert (need, avail) == (want, want)
+        with pytest.raises(B.BttbError) as e:
+            B.bttb_plan_memory_check(h, nrhs, want - 1)
+        assert e.value.status == 7 and "need" in str(e.value)
+        n, a = ctypes.c_size_t(), ctypes.c_size_t()
+        st = lib.bttb_plan_memory_check(ctypes.c_void_p(h), nrhs, want - 1, ctypes.byref(n), ctypes.byref(a))
+        assert st == 7 and (n.value, a.value) == (want, want - 1)
+        assert lib.bttb_plan_memory_check(ctypes.c_void_p(h), 0, want, None, None) == 1
+        B.bttb_plan_destroy(h)
+    assert _lib.load().bttb_plan_memory_check(None, 1, 1, None, None) == 2
+    # the 1024 x 1024 x 128 FP32 volume with its spectra and workspace needs
+    # about 2.03 GiB
+    h = B.bttb_plan_create(W.gravity_1024(), "fp32")
+    B.bttb_plan_memory_check(h, 1, 3 << 30)
+    with pytest.raises(B.BttbError):
+        B.bttb_plan_memory_check(h, 1, 2 << 30)
     B.bttb_plan_destroy(h)
 
 
