@@ -282,7 +282,9 @@ k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
             }
         }
     };
-    constexpr bool PIPE = true;
+    // the 12-point lines have no registers left for the next layer's loads
+    // (they would spill): they load each layer when they reach it
+    constexpr bool PIPE = FftShape<N>::POW2;
     if (PIPE) load_layer(rb);
     for (int r = rb; r < re; ++r) {
         if (!PIPE) load_layer(r);
@@ -469,7 +471,9 @@ k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
     };
     int cur_k = -1, cur_key = -1;
     cT<T> rh[P];
-    constexpr bool PIPE = true;
+    // the 12-point lines have no registers left for the next layer's loads
+    // (they would spill): they load each layer when they reach it
+    constexpr bool PIPE = FftShape<N>::POW2;
     if (PIPE && u0 < u1) load_spec(u0);
     for (int u = u0; u < u1; ++u) {
         if (!PIPE) load_spec(u);
