@@ -165,26 +165,46 @@ template <typename T> __device__ __forceinline__ cT<T> phase(int a, int Na, int 
     return mk<T>((T)c, (T)s);
 }
 
-// The real even form's stored values of layer r for one line of positions
-// t + m TPL: .x = R(kx, ky); for the packed column (kx = 0 and kx = Nx/2)
-// .y = (-1)^pxl R(Nx/2, ky), the x phase at Nx/2 folded in.
+// The real even form's stored values R(kx, ky) of layer r for one line of
+// positions t + m TPL of column `col` (for the packed column, kx = 0).
 template <typename T, int N>
-__device__ __forceinline__ void load_real_even(cT<T> (&tn)[FftShape<N>::P], const ColJob& J, int r, int col,
-                                               bool packed, int t)
+__device__ __forceinline__ void load_real_even(T (&tn)[FftShape<N>::P], const ColJob& J, int r, int col, int t)
 {
     constexpr int P = FftShape<N>::P;
     const T* sp = (const T*)J.spec + ((int64_t)r * (J.ncols + 1) + col) * J.lds;
 #pragma unroll
-    for (int m = 0; m < P; ++m) tn[m].x = sp[fold_idx<N>(t, m)];
-    if (packed) {
-        const T sgn = (J.px & 1) ? (T)-1 : (T)1;
-        const T* sq = (const T*)J.spec + ((int64_t)r * (J.ncols + 1) + J.ncols) * J.lds;
+    for (int m = 0; m < P; ++m) tn[m] = sp[fold_idx<N>(t, m)];
+}
+// The packed column's second part: (-1)^pxl R(Nx/2, ky), the x phase at
+// Nx/2 folded in.
+template <typename T, int N>
+__device__ __forceinline__ void load_real_even_nyq(T (&th)[FftShape<N>::P], const ColJob& J, int r, int t)
+{
+    constexpr int P = FftShape<N>::P;
+    const T sgn = (J.px & 1) ? (T)-1 : (T)1;
+    const T* sq = (const T*)J.spec + ((int64_t)r * (J.ncols + 1) + J.ncols) * J.lds;
 #pragma unroll
-        for (int m = 0; m < P; ++m) tn[m].y = sgn * sq[fold_idx<N>(t, m)];
+    for (int m = 0; m < P; ++m) th[m] = sgn * sq[fold_idx<N>(t, m)];
+}
+
+// Both parts in one complex value per position (.x = R(kx, ky); for the
+// packed column .y = (-1)^pxl R(Nx/2, ky), else 0): the transpose kernel's
+// form, whose register allocation is best with complex spectra.
+template <typename T, int N>
+__device__ __forceinline__ void load_real_even_c(cT<T> (&tn)[FftShape<N>::P], const ColJob& J, int r, int col,
+                                                 bool packed, int t)
+{
+    constexpr int P = FftShape<N>::P;
+    T re[P], im[P];
+    load_real_even<T, N>(re, J, r, col, t);
+    if (packed) {
+        load_real_even_nyq<T, N>(im, J, r, t);
     } else {
 #pragma unroll
-        for (int m = 0; m < P; ++m) tn[m].y = (T)0;
+        for (int m = 0; m < P; ++m) im[m] = (T)0;
     }
+#pragma unroll
+    for (int m = 0; m < P; ++m) tn[m] = mk<T>(re[m], im[m]);
 }
 
 // End of the forward column pass for one line: the depth sum w of column
@@ -261,15 +281,19 @@ k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
     const bool zhi = ny <= N / 2;
     const int ccol = ok ? col : 0;
     // software pipeline: the next layer's spectra and input columns are
-    // loaded while the current layer is transformed
-    cT<T> tn[P], xn[NR][P];
+    // loaded while the current layer is transformed.  Real even spectra are
+    // real except in the packed column, whose second part (the values at
+    // kx = Nx/2) is loaded when it is used.
+    using S = std::conditional_t<SF == FORM_REAL_EVEN, T, cT<T>>;
+    S tn[P];
+    cT<T> xn[NR][P];
     auto load_layer = [&](int r) {
         if constexpr (SF == FORM_COMPLEX) {
             const cT<T>* sp = spec + ((int64_t)r * ncols + ccol) * N;
 #pragma unroll
             for (int m = 0; m < P; ++m) tn[m] = sp[t + m * TPL];
         } else {
-            load_real_even<T, N>(tn, J, r, ccol, packed, t);
+            load_real_even<T, N>(tn, J, r, ccol, t);
         }
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
@@ -288,7 +312,8 @@ k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
     if (PIPE) load_layer(rb);
     for (int r = rb; r < re; ++r) {
         if (!PIPE) load_layer(r);
-        cT<T> tv[P], v[NR][P];
+        S tv[P];
+        cT<T> v[NR][P];
 #pragma unroll
         for (int m = 0; m < P; ++m) tv[m] = tn[m];
 #pragma unroll
@@ -324,17 +349,19 @@ k_cols_fwd_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
                     stage_line<T, N>(v[q], xl, t, packed);
                     if (packed) {
                         // R(0) F0 + i (-1)^pxl R(Nx/2) F1 (R is even: no mirror)
+                        T th[P];
+                        load_real_even_nyq<T, N>(th, J, r, t);
 #pragma unroll
                         for (int m = 0; m < P; ++m) {
                             const cT<T> vr = xl[mirror_idx<N>(t, m)];
                             const cT<T> a = herm_a<T>(v[q][m], vr), b = herm_b<T>(v[q][m], vr);
-                            acc[q][m].add(mk<T>(tv[m].x * a.x - tv[m].y * b.y, tv[m].x * a.y + tv[m].y * b.x));
+                            acc[q][m].add(mk<T>(tv[m] * a.x - th[m] * b.y, tv[m] * a.y + th[m] * b.x));
                         }
                         continue;
                     }
                 }
 #pragma unroll
-                for (int m = 0; m < P; ++m) acc[q][m].add(mk<T>(tv[m].x * v[q][m].x, tv[m].x * v[q][m].y));
+                for (int m = 0; m < P; ++m) acc[q][m].add(mk<T>(tv[m] * v[q][m].x, tv[m] * v[q][m].y));
             }
         }
     }
@@ -466,7 +493,7 @@ k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
 #pragma unroll
             for (int m = 0; m < P; ++m) tn[m] = sp[t + m * TPL];
         } else {
-            load_real_even<T, N>(tn, J, J.r0 + l, ccol, cb == 0 && cl == 0, t);
+            load_real_even_c<T, N>(tn, J, J.r0 + l, ccol, cb == 0 && cl == 0, t);
         }
     };
     int cur_k = -1, cur_key = -1;
