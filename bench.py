@@ -109,7 +109,11 @@ def pair_bytes(pr, Nx, Ny, esz, form):
 
 # the sources that define the product kernels (their traffic does not depend
 # on the host code)
-KERNEL_SOURCES = ["bttb_kernels.hip", "bttb_cols.hip", "fft_core.h", "kern_common.h", "bttb_internal.h"]
+# every source of the product kernels (the host code and the CGLS vector
+# kernels excluded)
+KERNEL_SOURCES = ["bttb_kernels.hip", "bttb_cols.hip", "bttb_cols_a.hip", "bttb_cols_b.hip", "bttb_cols_c.hip",
+                  "bttb_cols_d.hip", "bttb_rows_a.hip", "bttb_rows_b.hip", "bttb_rows_c.hip", "bttb_rows_d.hip",
+                  "cols_impl.h", "rows_impl.h", "fft_core.h", "kern_common.h", "bttb_internal.h"]
 
 
 def kernel_source_hash():

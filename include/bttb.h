@@ -361,8 +361,11 @@ bttb_status bttb_batch_destroy(bttb_batch_t batch);
  * row_tile in {2, 4, 8} (wavefronts per block of the row transforms),
  * col_tile in {1, 2} and layer_chunk in {0, 8, 16, 32} below nz -- and
  * return the descriptor with the fastest one filled in (nx_fft, ny_fft,
- * row_tile, col_tile, layer_chunk).  The lengths change the products only by
- * rounding.
+ * row_tile, col_tile, layer_chunk).  Each candidate runs one forward and one
+ * transpose product on seeded uniform inputs, once untimed and then 5 timed
+ * times, and counts its fastest time; the plan's default configuration is
+ * timed first and another candidate replaces the best so far only when it is
+ * at least 2 % faster.  The lengths change the products only by rounding.
  * Results are cached in a text file (path: environment variable
  * BTTB_TUNE_CACHE, default $HOME/.cache/bttb_autotune.txt), keyed by the
  * shape, precision, accumulation, nrhs and device; a cached key is returned

@@ -101,6 +101,7 @@ template <> struct cplx<double> { using type = double2; };
 template <typename T> using cT = typename cplx<T>::type;
 
 hipError_t launch_twiddles(double2* t64, float2* t32, int n, hipStream_t s);
+hipError_t launch_fill_uniform(void* p, int64_t n, bool fp64, uint32_t seed, hipStream_t s);
 // corner grid of the depth edges z_{r0} .. z_{r0 + nl} into P.corners
 // (gravity / magnetic), then the generator of layers [r0, r0 + nl)
 hipError_t launch_corners(const GenParams& P, int nl, double* corners, hipStream_t s);

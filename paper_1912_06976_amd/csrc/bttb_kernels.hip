@@ -169,6 +169,32 @@ __global__ void k_generate(GenParams P, int r0, double* __restrict__ out)
 // launchers (dispatch on the transform lengths)
 // ---------------------------------------------------------------------------
 
+// Seeded values uniform in [-0.5, 0.5): an integer hash of the index (the
+// autotuner's synthetic inputs, so that timings see data of ordinary bit
+// activity).  Grid-stride loop: every index below n, any grid.
+template <typename T>
+__global__ void k_fill_uniform(T* __restrict__ p, int64_t n, uint32_t seed)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t h = (uint32_t)i * 0x9E3779B1u ^ seed ^ (uint32_t)(i >> 32);
+        h ^= h >> 16;
+        h *= 0x85EBCA6Bu;
+        h ^= h >> 13;
+        h *= 0xC2B2AE35u;
+        h ^= h >> 16;
+        p[i] = (T)((double)h * (1.0 / 4294967296.0) - 0.5);
+    }
+}
+
+hipError_t launch_fill_uniform(void* p, int64_t n, bool fp64, uint32_t seed, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    if (fp64) hipLaunchKernelGGL(k_fill_uniform<double>, dim3(blocks), dim3(256), 0, s, (double*)p, n, seed);
+    else hipLaunchKernelGGL(k_fill_uniform<float>, dim3(blocks), dim3(256), 0, s, (float*)p, n, seed);
+    return hipGetLastError();
+}
+
 hipError_t launch_twiddles(double2* t64, float2* t32, int n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_twiddles, dim3((n + 255) / 256), dim3(256), 0, s, t64, t32, n);

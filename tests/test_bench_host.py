@@ -39,6 +39,13 @@ def test_algorithmic_bytes_of_the_bench_volume():
     assert kf["fwd_cols_fft_mac"] > 1024 * 128 * 5 * 2048 * 11
 
 
+def test_kernel_source_hash_covers_every_kernel_source():
+    import bench
+    src = os.path.join(ROOT, "paper_1912_06976_amd", "csrc")
+    kernel_files = {f for f in os.listdir(src) if f.endswith((".hip", ".h"))} - {"bttb_host.hip", "bttb_cgls.hip"}
+    assert kernel_files == set(bench.KERNEL_SOURCES)
+
+
 def test_kernel_source_hash_ignores_comments(tmp_path, monkeypatch):
     import bench
     h0 = bench.kernel_source_hash()
