@@ -322,9 +322,35 @@ def run_autograd(torch, B, steps):
     e1.record()
     torch.cuda.synchronize()
     ms_step = e0.elapsed_time(e1) / steps
+    # the same step captured once in a HIP graph (torch.cuda.graph) and
+    # replayed: the GPU time without the host's per-call overhead (the eager
+    # step above is bound by the host's launches)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(3):
+            step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    mg = m0.clone().requires_grad_(True)
+    with torch.cuda.graph(graph):
+        loss_g = 0.5 * (B.bttb_matvec(plan, mg) - d).pow(2).sum()
+        grad_g, = torch.autograd.grad(loss_g, mg)
+    graph.replay()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(grad_g, step()))
+    e0.record()
+    for _ in range(steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1) / steps
     nx, ny, nz = W.dims(pr)
     return {"workload": "magnetic 288x288x48 FP32, loss 0.5||Gm-d||^2 forward + backward",
-            "ms_per_step": round(ms_step, 4), "cells_per_s": nx * ny * nz / (ms_step * 1e-3)}
+            "fft": "%dx%d" % (plan.nx_fft, plan.ny_fft),
+            "ms_per_step": round(ms_step, 4), "cells_per_s": nx * ny * nz / (ms_step * 1e-3),
+            "graph_ms_per_step": round(ms_graph, 4), "graph_equals_eager": same}
 
 
 def main():

@@ -35,6 +35,15 @@ def _stream_obj(stream):
     return torch.cuda.current_stream() if stream is None else stream
 
 
+def _empty_on(s, is_current: bool, shape, dtype, device) -> torch.Tensor:
+    """torch.empty allocated on stream s (s is torch's current stream when
+    is_current: no stream switch needed)."""
+    if is_current:
+        return torch.empty(shape, dtype=dtype, device=device)
+    with torch.cuda.stream(s):
+        return torch.empty(shape, dtype=dtype, device=device)
+
+
 def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
     return ctypes.c_void_p(int(t.data_ptr()))
 
@@ -245,6 +254,7 @@ class Plan:
         self.ny = self.sy + problem.get("pyl", 0) + problem.get("pyr", 0)
         self.spectra = None
         self._ws = {}          # cached workspace per stream (keyed by the HIP stream handle)
+        self._ws_bytes = {}    # workspace bytes per right-hand-side count
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -257,7 +267,10 @@ class Plan:
 
     # -- memory -----------------------------------------------------------
     def workspace_bytes(self, nrhs: int = 1) -> int:
-        return bttb_plan_query(self.handle, nrhs)[1]
+        b = self._ws_bytes.get(nrhs)
+        if b is None:
+            b = self._ws_bytes[nrhs] = bttb_plan_query(self.handle, nrhs)[1]
+        return b
 
     def workspace(self, nrhs: int = 1, stream=None) -> torch.Tensor:
         """The workspace of products with nrhs right-hand sides on `stream`
@@ -297,7 +310,7 @@ class Plan:
         return self
 
     def _check_vec(self, t: torch.Tensor, tail, name):
-        if t.device.type != "cuda" or t.dtype != self.dtype or not t.is_contiguous():
+        if not t.is_cuda or t.dtype != self.dtype or not t.is_contiguous():
             raise ValueError("%s must be a contiguous %s CUDA tensor" % (name, self.dtype))
         if tuple(t.shape[-len(tail):]) != tuple(tail):
             raise ValueError("%s has shape %s, expected [..., %s]" % (name, tuple(t.shape), tail))
@@ -307,28 +320,28 @@ class Plan:
         if self.spectra is None:
             raise RuntimeError("call generate() first")
         nrhs = self._check_vec(m, (self.nz, self.ny, self.nx), "m")
+        s = _stream_obj(stream)
         if out is None:
-            with torch.cuda.stream(_stream_obj(stream)):
-                out = torch.empty(m.shape[:-3] + (self.sy, self.sx), dtype=self.dtype, device=m.device)
+            out = _empty_on(s, stream is None, m.shape[:-3] + (self.sy, self.sx), self.dtype, m.device)
         if self._check_vec(out, (self.sy, self.sx), "out") != nrhs:
             raise ValueError("out holds a different number of right-hand sides than m")
         if nrhs == 0:
             return out
-        bttb_forward(self.handle, self.spectra, m, out, nrhs, self.workspace(nrhs, stream), stream)
+        bttb_forward(self.handle, self.spectra, m, out, nrhs, self.workspace(nrhs, s), s)
         return out
 
     def transpose(self, r: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         if self.spectra is None:
             raise RuntimeError("call generate() first")
         nrhs = self._check_vec(r, (self.sy, self.sx), "r")
+        s = _stream_obj(stream)
         if out is None:
-            with torch.cuda.stream(_stream_obj(stream)):
-                out = torch.empty(r.shape[:-2] + (self.nz, self.ny, self.nx), dtype=self.dtype, device=r.device)
+            out = _empty_on(s, stream is None, r.shape[:-2] + (self.nz, self.ny, self.nx), self.dtype, r.device)
         if self._check_vec(out, (self.nz, self.ny, self.nx), "out") != nrhs:
             raise ValueError("out holds a different number of right-hand sides than r")
         if nrhs == 0:
             return out
-        bttb_transpose(self.handle, self.spectra, r, out, nrhs, self.workspace(nrhs, stream), stream)
+        bttb_transpose(self.handle, self.spectra, r, out, nrhs, self.workspace(nrhs, s), s)
         return out
 
     def cgls(self, d: torch.Tensor, lam: float, iterations: int, m0: torch.Tensor | None = None, stream=None):
