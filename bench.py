@@ -113,7 +113,7 @@ def pair_bytes(pr, Nx, Ny, esz, form):
 # kernels excluded)
 KERNEL_SOURCES = ["bttb_kernels.hip", "bttb_cols.hip", "bttb_cols_a.hip", "bttb_cols_b.hip", "bttb_cols_c.hip",
                   "bttb_cols_d.hip", "bttb_rows_a.hip", "bttb_rows_b.hip", "bttb_rows_c.hip", "bttb_rows_d.hip",
-                  "cols_impl.h", "rows_impl.h", "fft_core.h", "kern_common.h", "bttb_internal.h"]
+                  "cols_impl.h", "rows_impl.h", "rows_cfg.h", "fft_core.h", "kern_common.h", "bttb_internal.h"]
 
 
 def kernel_source_hash():

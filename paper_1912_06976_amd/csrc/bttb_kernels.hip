@@ -17,9 +17,9 @@
 //   k_rows_c2r       half spectra (panels) -> real rows along x, two rows per
 //                    complex transform, extraction of the leading columns
 //
-// The column kernels of the products are in cols_impl.h.  All kernels take
-// caller-owned device buffers; none allocates.
-#include "rows_impl.h"
+// The row kernels are in rows_impl.h, the column kernels of the products in
+// cols_impl.h.  All kernels take caller-owned device buffers; none allocates.
+#include "rows_cfg.h"
 
 namespace bttbk {
 

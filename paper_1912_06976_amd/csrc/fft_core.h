@@ -309,9 +309,11 @@ template <typename T, int N> struct LineTwiddles {
 
 // Alternative twiddle source: a stage-major table (typically in LDS) that
 // saves the registers of LineTwiddles.  Stage s >= 1 of radix R and span L
-// holds w^(i j N/(L R)) at [off(s) + (i-1) L + j], 1 <= i < R, j < L (for
-// powers of two: the radix-8 stages, L = 8^s, then the final radix-RL stage
-// at off(S8)).  A stage's reads by consecutive threads are consecutive (or
+// holds w^(i j N/(L R)) at [off(s) + (i-1) L + j], 1 <= i < R, j < L; for
+// powers of two the radix-8 stages (L = 8^s) hold only i = 1, 2, 4 at
+// [off(s) + k L + j], i = 2^k (the other four are their products, formed at
+// use by tw_stage8), and the final radix-RL stage sits at off(S8) in the
+// full form.  A stage's reads by consecutive threads are consecutive (or
 // broadcast) entries, so they do not conflict on the LDS banks.
 template <typename T, int N> struct TableTwiddles {
     using S = FftShape<N>;
@@ -321,7 +323,7 @@ template <typename T, int N> struct TableTwiddles {
         int o = 0;
         if constexpr (S::POW2) {
             int L = 8;
-            for (int k = 1; k < s; ++k) { o += 7 * L; L *= 8; }
+            for (int k = 1; k < s; ++k) { o += 3 * L; L *= 8; }
         } else {
             for (int k = 1; k < s; ++k) o += (mr_radix(N, k) - 1) * mr_span(N, k);
         }
@@ -337,9 +339,11 @@ template <typename T, int N> struct TableTwiddles {
             for (int e = tid; e < size(); e += nthreads) {
                 int idx;
                 if (e < off(S::S8)) {
+                    // radix-8 stage s: w^j, w^(2j), w^(4j) (w = the stage's
+                    // root), component-major
                     int s = 1, L = 8;
                     while (e >= off(s + 1)) { ++s; L *= 8; }
-                    const int r = e - off(s), i = r / L + 1, j = r % L;
+                    const int r = e - off(s), i = 1 << (r / L), j = r % L;
                     idx = i * j * (N / (8 * L));
                 } else {
                     const int L = N / S::RL, r = e - off(S::S8), i = r / L + 1, j = r % L;
@@ -366,6 +370,75 @@ template <typename T, int N>
 __device__ __forceinline__ cT<T> tw_get(const LineTwiddles<T, N>& tw, int c, int, int, int, int) { return tw.w[c]; }
 template <typename T, int N>
 __device__ __forceinline__ cT<T> tw_get(const TableTwiddles<T, N>& tw, int, int s, int L, int i, int j) {
+    return tw.p[TableTwiddles<T, N>::off(s) + (i - 1) * L + j];
+}
+// product a b with the contraction written out (the table route forms four
+// of a radix-8 butterfly's seven twiddles this way; every kernel that reads
+// the table thus gets the same values)
+template <typename T> __device__ __forceinline__ cT<T> cmul_fixed(cT<T> a, cT<T> b) {
+    if constexpr (sizeof(T) == 4)
+        return mk<T>(__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.x, b.y, a.y * b.x));
+    else
+        return mk<T>(__builtin_fma(a.x, b.x, -(a.y * b.y)), __builtin_fma(a.x, b.y, a.y * b.x));
+}
+// the seven twiddles w^(i j), i = 1..7, of radix-8 stage s (span L) for
+// butterfly j: from registers, or from the table's w^j, w^(2j), w^(4j) and
+// their products (three LDS reads instead of seven)
+template <typename T, int N>
+__device__ __forceinline__ void tw_stage8(const LineTwiddles<T, N>& tw, int c, int, int, int, cT<T> (&w)[7]) {
+#pragma unroll
+    for (int i = 0; i < 7; ++i) w[i] = tw.w[c + i];
+}
+template <typename T, int N>
+__device__ __forceinline__ void tw_stage8(const TableTwiddles<T, N>& tw, int, int s, int L, int j, cT<T> (&w)[7]) {
+    const cT<T>* q = tw.p + TableTwiddles<T, N>::off(s) + j;
+    const cT<T> w1 = q[0], w2 = q[L], w4 = q[2 * L];
+    const cT<T> w3 = cmul_fixed<T>(w1, w2);
+    w[0] = w1;
+    w[1] = w2;
+    w[2] = w3;
+    w[3] = w4;
+    w[4] = cmul_fixed<T>(w1, w4);
+    w[5] = cmul_fixed<T>(w2, w4);
+    w[6] = cmul_fixed<T>(w3, w4);
+}
+// Twiddles of a kernel whose threads each keep one position t in every
+// transform (the row kernels), powers of two: the three stored powers w^j,
+// w^(2j), w^(4j) of each radix-8 stage in registers (j = t mod L is fixed
+// per thread), the final radix-RL stage read from the table.  The values
+// equal TableTwiddles' bit for bit (the same entries, the same products).
+template <typename T, int N> struct RegTableTwiddles {
+    using S = FftShape<N>;
+    static_assert(S::POW2, "register-held radix-8 powers need a power-of-two length");
+    cT<T> b[S::S8 > 1 ? S::S8 - 1 : 1][3];
+    const cT<T>* p;            // the table (built by TableTwiddles::build)
+    // tw: the natural table in global memory; tab: the LDS table
+    __device__ __forceinline__ void load(const cT<T>* __restrict__ tw, const cT<T>* tab, int t) {
+        p = tab;
+        int L = 8;
+#pragma unroll
+        for (int s = 1; s < S::S8; ++s) {
+            const int j = t % L, step = N / (8 * L);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) b[s - 1][k] = tw[((1 << k) * j * step) & (N - 1)];
+            L *= 8;
+        }
+    }
+};
+template <typename T, int N>
+__device__ __forceinline__ void tw_stage8(const RegTableTwiddles<T, N>& tw, int, int s, int, int, cT<T> (&w)[7]) {
+    const cT<T> w1 = tw.b[s - 1][0], w2 = tw.b[s - 1][1], w4 = tw.b[s - 1][2];
+    const cT<T> w3 = cmul_fixed<T>(w1, w2);
+    w[0] = w1;
+    w[1] = w2;
+    w[2] = w3;
+    w[3] = w4;
+    w[4] = cmul_fixed<T>(w1, w4);
+    w[5] = cmul_fixed<T>(w2, w4);
+    w[6] = cmul_fixed<T>(w3, w4);
+}
+template <typename T, int N>
+__device__ __forceinline__ cT<T> tw_get(const RegTableTwiddles<T, N>& tw, int, int s, int L, int i, int j) {
     return tw.p[TableTwiddles<T, N>::off(s) + (i - 1) * L + j];
 }
 // the same for stage S of a 12-point transform (the table offset a constant)
@@ -405,8 +478,10 @@ __device__ __forceinline__ void fft_line_p2(cT<T> (&v)[8], cT<T>* __restrict__ l
         // radix-8 butterfly b = t: inputs at t + i * TPL = v[i]
         if (s > 0) {
             const int j = t % L;
+            cT<T> w[7];
+            tw_stage8<T, N>(tw, c, s, L, j, w);
 #pragma unroll
-            for (int i = 1; i < 8; ++i) v[i] = twmul<T, DIR>(v[i], tw_get<T, N>(tw, c + i - 1, s, L, i, j));
+            for (int i = 1; i < 8; ++i) v[i] = twmul<T, DIR>(v[i], w[i - 1]);
             c += 7;
         }
         if (ZERO_HI && s == 0) {

@@ -1,9 +1,9 @@
 // rows_impl.h -- gfx950 row transforms of the products and the column
 // transforms of the spectra (kernel templates and the launchers of one
 // transform length).  Included by bttb_rows_*.hip, which instantiate them for
-// groups of lengths, and by bttb_kernels.hip for the block shapes.
+// groups of lengths; the block shapes are in rows_cfg.h.
 #pragma once
-#include "kern_common.h"
+#include "rows_cfg.h"
 
 namespace bttbk {
 
@@ -23,45 +23,24 @@ template <int N> __device__ __forceinline__ int mirror_pos(int k)
     if constexpr (FftShape<N>::POW2) return (N - k) & (N - 1);
     else return k == 0 || k == N ? 0 : N - k;
 }
-// Row length of an LDS staging tile of k rows whose accesses by a
-// wavefront touch k rows at a few consecutive columns: the smallest
-// length >= n congruent to 32 / k modulo 32, so that those elements sit in
-// distinct 8-byte bank pairs (for many rows or short ones: an odd length).
-constexpr int spread_len(int n, int k)
+// Twiddles of the R2C row kernels: power-of-two lines keep the radix-8
+// stages' stored powers in registers and read the last stage from the LDS
+// table (one LDS read per twiddle fewer: 0.39 -> 0.35 ms for the 2048-point
+// rows of a 1024 x 1024 x 128 volume); 4096-point lines (three such stages
+// would spill) and 12-point lines read every stage from the table.
+template <typename T, int N>
+using RowTwiddles =
+    std::conditional_t<FftShape<N>::POW2 && N <= 2048, RegTableTwiddles<T, N>, TableTwiddles<T, N>>;
+template <typename T, int N>
+__device__ __forceinline__ void row_twiddles(RegTableTwiddles<T, N>& w, const cT<T>* __restrict__ tw, cT<T>* tab, int t)
 {
-    if (k >= 32 || n < 32) return n % 2 ? n : n + 1;
-    const int r = 32 / k;
-    return n + ((r - n) % 32 + 32) % 32;
+    w.load(tw, tab, t);
 }
-// P0: pairs of rows per block for long rows (a tuning choice, 2 or 4)
-template <typename T, int N, int P0 = 4> struct RowCfg {
-    static constexpr int TPL = FftShape<N>::TPL;
-    static constexpr int P = FftShape<N>::P;     // points per thread
-    static constexpr int LPB = lines_per_block(TPL);
-    static constexpr int PAIRS = sizeof(T) == 4 ? (N <= 2048 ? (LPB > P0 ? LPB : P0) : 2)
-                                                : (N <= 1024 ? (LPB > P0 ? LPB : P0) : (N <= 2048 ? 2 : 1));
-    static constexpr int RT = 2 * PAIRS;            // rows per block
-    static constexpr int THREADS = PAIRS * TPL;
-    static constexpr int HALF = N / 2;              // packed half-spectrum columns
-    static constexpr int XCH = PAIRS * lds_line_elems(N);
-    // c2r: the tile of packed half spectra staged [row][kx], row length CR:
-    // the tile's loads (RT rows of a few kx per wavefront) and the line
-    // reads (consecutive kx of one row) fall on distinct banks
-    static constexpr int CR = spread_len(HALF, RT);
-    static constexpr int CSTAGE = RT * CR;
-    static constexpr int LDS = CSTAGE > XCH ? CSTAGE : XCH;
-    static constexpr int TWO = LDS;                 // offset of the LDS twiddle table
-    // r2c (FP32): the complex transforms Z of the PAIRS row pairs staged
-    // [pair][k], row length ZR (the writes of a line are consecutive, the
-    // split's reads take PAIRS pairs of a few k)
-    static constexpr int ZR = spread_len(N, PAIRS);
-    static constexpr int ZSTAGE = PAIRS * ZR;
-    // r2c (FP64): the half spectra of the RT rows staged [kx][row] (split
-    // through the line buffers first, which measured faster there)
-    static constexpr int SROW = RT + 1;
-    static constexpr int STAGE = HALF * SROW;
-    static constexpr int LDS_R2C = sizeof(T) == 4 ? (ZSTAGE > XCH ? ZSTAGE : XCH) : (STAGE > XCH ? STAGE : XCH);
-};
+template <typename T, int N>
+__device__ __forceinline__ void row_twiddles(TableTwiddles<T, N>& w, const cT<T>* __restrict__, cT<T>* tab, int)
+{
+    w.p = tab;
+}
 
 // Row kernels are persistent: gridDim.x blocks (about the number that fit on
 // the device at once) walk over the row groups g = lb, lb + G, lb + 2G, ...
@@ -86,7 +65,8 @@ k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
     const int pr = threadIdx.x / TPL, t = threadIdx.x % TPL;
     TableTwiddles<T, N>::build(lds + C::LDS_R2C, tw, threadIdx.x, C::THREADS);
     __syncthreads();
-    const TableTwiddles<T, N> twl{lds + C::LDS_R2C};
+    RowTwiddles<T, N> twl;
+    row_twiddles(twl, tw, lds + C::LDS_R2C, threadIdx.x % C::TPL);
     cT<T>* xl = lds + pr * lds_line_elems(N);
     auto load = [&](int g, cT<T> (&v)[P]) {
         const RowJob& J = jobs.j[find_job(jobs, g)];
@@ -209,6 +189,8 @@ k_rows_c2r(RowJobs jobs, const cT<T>* __restrict__ tw)
     const int pr = threadIdx.x / TPL, t = threadIdx.x % TPL;
     TableTwiddles<T, N>::build(lds + C::TWO, tw, threadIdx.x, C::THREADS);
     __syncthreads();
+    // (the table for every stage: with the radix-8 powers in registers this
+    // kernel would exceed the 128 registers of its 16-wave block)
     const TableTwiddles<T, N> twl{lds + C::TWO};
     cT<T>* xl = lds + pr * lds_line_elems(N);
     // tile of the packed half spectra of RT rows: HALF * RT = P * THREADS
@@ -303,7 +285,8 @@ k_rows_r2c_t(RowJobs jobs, const cT<T>* __restrict__ tw)
     __shared__ cT<T> lds[C::LPB * LL + TableTwiddles<T, N>::size()];
     TableTwiddles<T, N>::build(lds + C::LPB * LL, tw, threadIdx.x, C::THREADS);
     __syncthreads();
-    const TableTwiddles<T, N> twl{lds + C::LPB * LL};
+    RowTwiddles<T, N> twl;
+    row_twiddles(twl, tw, lds + C::LPB * LL, threadIdx.x % C::TPL);
     const int tl = threadIdx.x / TPL, t = threadIdx.x % TPL;
     cT<T>* xl = lds + tl * LL;
     const int total = jobs.total;
