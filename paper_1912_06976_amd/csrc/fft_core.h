@@ -407,17 +407,18 @@ __device__ __forceinline__ void tw_stage8(const TableTwiddles<T, N>& tw, int, in
 // w^(2j), w^(4j) of each radix-8 stage in registers (j = t mod L is fixed
 // per thread), the final radix-RL stage read from the table.  The values
 // equal TableTwiddles' bit for bit (the same entries, the same products).
-template <typename T, int N> struct RegTableTwiddles {
+template <typename T, int N, int NREG = FftShape<N>::S8 - 1> struct RegTableTwiddles {
     using S = FftShape<N>;
     static_assert(S::POW2, "register-held radix-8 powers need a power-of-two length");
-    cT<T> b[S::S8 > 1 ? S::S8 - 1 : 1][3];
+    static constexpr int NR = NREG < S::S8 - 1 ? NREG : S::S8 - 1;   // radix-8 stages held in registers
+    cT<T> b[NR > 0 ? NR : 1][3];
     const cT<T>* p;            // the table (built by TableTwiddles::build)
     // tw: the natural table in global memory; tab: the LDS table
     __device__ __forceinline__ void load(const cT<T>* __restrict__ tw, const cT<T>* tab, int t) {
         p = tab;
         int L = 8;
 #pragma unroll
-        for (int s = 1; s < S::S8; ++s) {
+        for (int s = 1; s <= NR; ++s) {
             const int j = t % L, step = N / (8 * L);
 #pragma unroll
             for (int k = 0; k < 3; ++k) b[s - 1][k] = tw[((1 << k) * j * step) & (N - 1)];
@@ -425,8 +426,13 @@ template <typename T, int N> struct RegTableTwiddles {
         }
     }
 };
-template <typename T, int N>
-__device__ __forceinline__ void tw_stage8(const RegTableTwiddles<T, N>& tw, int, int s, int, int, cT<T> (&w)[7]) {
+template <typename T, int N, int NREG>
+__device__ __forceinline__ void tw_stage8(const RegTableTwiddles<T, N, NREG>& tw, int c, int s, int L, int j,
+                                          cT<T> (&w)[7]) {
+    if (s > RegTableTwiddles<T, N, NREG>::NR) {
+        tw_stage8<T, N>(TableTwiddles<T, N>{tw.p}, c, s, L, j, w);
+        return;
+    }
     const cT<T> w1 = tw.b[s - 1][0], w2 = tw.b[s - 1][1], w4 = tw.b[s - 1][2];
     const cT<T> w3 = cmul_fixed<T>(w1, w2);
     w[0] = w1;
@@ -437,8 +443,8 @@ __device__ __forceinline__ void tw_stage8(const RegTableTwiddles<T, N>& tw, int,
     w[5] = cmul_fixed<T>(w2, w4);
     w[6] = cmul_fixed<T>(w3, w4);
 }
-template <typename T, int N>
-__device__ __forceinline__ cT<T> tw_get(const RegTableTwiddles<T, N>& tw, int, int s, int L, int i, int j) {
+template <typename T, int N, int NREG>
+__device__ __forceinline__ cT<T> tw_get(const RegTableTwiddles<T, N, NREG>& tw, int, int s, int L, int i, int j) {
     return tw.p[TableTwiddles<T, N>::off(s) + (i - 1) * L + j];
 }
 // the same for stage S of a 12-point transform (the table offset a constant)
@@ -461,8 +467,16 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// a w (DIR < 0) or a conj(w) (DIR > 0), with the contraction into fused
+// multiply-adds written out: every kernel rounds a twiddle product the same
+// way, whatever its twiddles' source (registers or LDS)
+template <typename T> __device__ __forceinline__ T fma_t(T a, T b, T c) {
+    if constexpr (sizeof(T) == 4) return __builtin_fmaf(a, b, c);
+    else return __builtin_fma(a, b, c);
+}
 template <typename T, int DIR> __device__ __forceinline__ cT<T> twmul(cT<T> a, cT<T> w) {
-    return DIR < 0 ? cmul<T>(a, w) : cmulc<T>(a, w);
+    if constexpr (DIR < 0) return mk<T>(fma_t<T>(a.x, w.x, -(a.y * w.y)), fma_t<T>(a.x, w.y, a.y * w.x));
+    else return mk<T>(fma_t<T>(a.x, w.x, a.y * w.y), fma_t<T>(a.y, w.x, -(a.x * w.y)));
 }
 
 // Power-of-two lengths (8 points per thread).

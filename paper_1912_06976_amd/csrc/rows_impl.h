@@ -31,8 +31,14 @@ template <int N> __device__ __forceinline__ int mirror_pos(int k)
 template <typename T, int N>
 using RowTwiddles =
     std::conditional_t<FftShape<N>::POW2 && N <= 2048, RegTableTwiddles<T, N>, TableTwiddles<T, N>>;
+// The C2R kernels hold the first such stage only (both would take them past
+// the 128 registers of a 16-wave block).
 template <typename T, int N>
-__device__ __forceinline__ void row_twiddles(RegTableTwiddles<T, N>& w, const cT<T>* __restrict__ tw, cT<T>* tab, int t)
+using RowTwiddlesC2R =
+    std::conditional_t<FftShape<N>::POW2 && N <= 2048, RegTableTwiddles<T, N, 1>, TableTwiddles<T, N>>;
+template <typename T, int N, int NREG>
+__device__ __forceinline__ void row_twiddles(RegTableTwiddles<T, N, NREG>& w, const cT<T>* __restrict__ tw, cT<T>* tab,
+                                             int t)
 {
     w.load(tw, tab, t);
 }
@@ -189,9 +195,8 @@ k_rows_c2r(RowJobs jobs, const cT<T>* __restrict__ tw)
     const int pr = threadIdx.x / TPL, t = threadIdx.x % TPL;
     TableTwiddles<T, N>::build(lds + C::TWO, tw, threadIdx.x, C::THREADS);
     __syncthreads();
-    // (the table for every stage: with the radix-8 powers in registers this
-    // kernel would exceed the 128 registers of its 16-wave block)
-    const TableTwiddles<T, N> twl{lds + C::TWO};
+    RowTwiddlesC2R<T, N> twl;
+    row_twiddles(twl, tw, lds + C::TWO, threadIdx.x % C::TPL);
     cT<T>* xl = lds + pr * lds_line_elems(N);
     // tile of the packed half spectra of RT rows: HALF * RT = P * THREADS
     // elements, element e = threadIdx.x + i THREADS at (kx, row) = (e / RT, e % RT)
@@ -364,7 +369,8 @@ k_rows_c2r_t(RowJobs jobs, const cT<T>* __restrict__ tw)
     __shared__ cT<T> lds[C::LPB * LL + TableTwiddles<T, N>::size()];
     TableTwiddles<T, N>::build(lds + C::LPB * LL, tw, threadIdx.x, C::THREADS);
     __syncthreads();
-    const TableTwiddles<T, N> twl{lds + C::LPB * LL};
+    RowTwiddlesC2R<T, N> twl;
+    row_twiddles(twl, tw, lds + C::LPB * LL, threadIdx.x % C::TPL);
     const int tl = threadIdx.x / TPL, t = threadIdx.x % TPL;
     cT<T>* xl = lds + tl * LL;
     const int total = jobs.total;
