@@ -35,6 +35,14 @@ def _stream_obj(stream):
     return torch.cuda.current_stream() if stream is None else stream
 
 
+def _capturing(s, is_current: bool) -> bool:
+    """Whether stream s is being captured into a graph."""
+    if is_current:
+        return torch.cuda.is_current_stream_capturing()
+    with torch.cuda.stream(s):
+        return torch.cuda.is_current_stream_capturing()
+
+
 def _empty_on(s, is_current: bool, shape, dtype, device) -> torch.Tensor:
     """torch.empty allocated on stream s (s is torch's current stream when
     is_current: no stream switch needed)."""
@@ -276,10 +284,18 @@ class Plan:
         """The workspace of products with nrhs right-hand sides on `stream`
         (default: the current stream), cached per stream and allocated on it:
         a larger replacement frees the old block on the same stream, after
-        the products already queued there."""
-        s = _stream_obj(stream)
+        the products already queued there.  During graph capture a fresh,
+        uncached workspace comes from the graph's memory pool."""
+        return self._workspace(nrhs, _stream_obj(stream), stream is None)
+
+    def _workspace(self, nrhs: int, s, is_current: bool) -> torch.Tensor:
         key = int(s.cuda_stream)
         need = self.workspace_bytes(nrhs)
+        if _capturing(s, is_current):
+            # under graph capture: a workspace of the graph's own memory pool,
+            # not cached (it must not be reused outside the graph)
+            with torch.cuda.stream(s):
+                return torch.empty(need, dtype=torch.uint8, device=self.device)
         ws = self._ws.get(key)
         if ws is None or ws.numel() < need:
             self._ws.pop(key, None)
@@ -327,7 +343,7 @@ class Plan:
             raise ValueError("out holds a different number of right-hand sides than m")
         if nrhs == 0:
             return out
-        bttb_forward(self.handle, self.spectra, m, out, nrhs, self.workspace(nrhs, s), s)
+        bttb_forward(self.handle, self.spectra, m, out, nrhs, self._workspace(nrhs, s, stream is None), s)
         return out
 
     def transpose(self, r: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
@@ -341,7 +357,7 @@ class Plan:
             raise ValueError("out holds a different number of right-hand sides than r")
         if nrhs == 0:
             return out
-        bttb_transpose(self.handle, self.spectra, r, out, nrhs, self.workspace(nrhs, s), s)
+        bttb_transpose(self.handle, self.spectra, r, out, nrhs, self._workspace(nrhs, s, stream is None), s)
         return out
 
     def cgls(self, d: torch.Tensor, lam: float, iterations: int, m0: torch.Tensor | None = None, stream=None):

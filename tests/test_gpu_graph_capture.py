@@ -105,3 +105,38 @@ def test_products_replay_equal_eager(torch_cuda, prec):
         assert torch.equal(mt, mt_ref), "replay %d" % k
         assert torch.equal(d_na, d_ref), "replay %d" % k
     assert np.isfinite(d.double().cpu().numpy()).all()
+
+
+def test_plan_methods_under_capture(torch_cuda):
+    """Plan.forward / Plan.transpose inside a captured graph: outputs and the
+    workspace come from the graph's memory pool (the workspace is not cached
+    for later eager calls); replays and later eager calls on every stream
+    equal the eager results bit for bit."""
+    from paper_1912_06976_amd import Plan
+    torch = torch_cuda
+    pr = W.magnetic_48x56()
+    plan = Plan(pr, "fp32").generate()
+    m = torch.tensor(W.uniform_model(pr, 21), dtype=plan.dtype, device="cuda")
+    r = torch.tensor(W.normal_data(pr, 22), dtype=plan.dtype, device="cuda")
+    d_ref, mt_ref = plan.forward(m), plan.transpose(r)
+    torch.cuda.synchronize()
+    cached = dict(plan._ws)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=s):
+        d_g = plan.forward(m)
+        mt_g = plan.transpose(r)
+    torch.cuda.synchronize()
+    # nothing of the graph's pool was cached
+    assert set(plan._ws) == set(cached) and all(plan._ws[k] is cached[k] for k in cached)
+    for k in range(3):
+        plan.transpose(plan.forward(m))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(d_g, d_ref) and torch.equal(mt_g, mt_ref), "replay %d" % k
+        with torch.cuda.stream(s):
+            e = plan.forward(m)
+        torch.cuda.synchronize()
+        assert torch.equal(e, d_ref)
