@@ -23,19 +23,18 @@ template <int N> __device__ __forceinline__ int mirror_pos(int k)
     if constexpr (FftShape<N>::POW2) return (N - k) & (N - 1);
     else return k == 0 || k == N ? 0 : N - k;
 }
-// Twiddles of the R2C row kernels: power-of-two lines keep the radix-8
+// Twiddles of the R2C row kernels: 2048-point lines keep the radix-8
 // stages' stored powers in registers and read the last stage from the LDS
-// table (one LDS read per twiddle fewer: 0.39 -> 0.35 ms for the 2048-point
-// rows of a 1024 x 1024 x 128 volume); 4096-point lines (three such stages
-// would spill) and 12-point lines read every stage from the table.
+// table (0.39 -> 0.35 ms for the rows of a 1024 x 1024 x 128 volume); other
+// lengths read every stage from the table (in registers the 1024-point
+// kernel would pass 128 registers, and with them the occupancy its blocks
+// need; 4096 would spill).
 template <typename T, int N>
-using RowTwiddles =
-    std::conditional_t<FftShape<N>::POW2 && N <= 2048, RegTableTwiddles<T, N>, TableTwiddles<T, N>>;
+using RowTwiddles = std::conditional_t<N == 2048, RegTableTwiddles<T, N>, TableTwiddles<T, N>>;
 // The C2R kernels hold the first such stage only (both would take them past
 // the 128 registers of a 16-wave block).
 template <typename T, int N>
-using RowTwiddlesC2R =
-    std::conditional_t<FftShape<N>::POW2 && N <= 2048, RegTableTwiddles<T, N, 1>, TableTwiddles<T, N>>;
+using RowTwiddlesC2R = std::conditional_t<N == 2048, RegTableTwiddles<T, N, 1>, TableTwiddles<T, N>>;
 template <typename T, int N, int NREG>
 __device__ __forceinline__ void row_twiddles(RegTableTwiddles<T, N, NREG>& w, const cT<T>* __restrict__ tw, cT<T>* tab,
                                              int t)
