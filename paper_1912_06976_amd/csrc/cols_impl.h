@@ -50,7 +50,7 @@ template <typename T, int N>
 __device__ __forceinline__ void init_twiddles(TableTwiddles<T, N>& w, const cT<T>* __restrict__ tw, cT<T>* tab, int)
 {
     TableTwiddles<T, N>::build(tab, tw, threadIdx.x, blockDim.x);
-    __syncthreads();
+    lds_barrier();
     w.p = tab;
 }
 
@@ -107,19 +107,19 @@ template <typename T, int N>
 __device__ __forceinline__ void stage_line(const cT<T> (&u)[FftShape<N>::P], cT<T>* bu, int t, bool active)
 {
     constexpr int TPL = FftShape<N>::TPL;
-    __syncthreads();
+    lds_barrier();
     if (active) {
 #pragma unroll
         for (int m = 0; m < FftShape<N>::P; ++m) bu[lpad(t + m * TPL)] = u[m];
     }
-    __syncthreads();
+    lds_barrier();
 }
 template <typename T, int N>
 __device__ __forceinline__ void stage_pair(const cT<T> (&u)[FftShape<N>::P], const cT<T> (&w)[FftShape<N>::P],
                                            cT<T>* bu, cT<T>* bw, int t, bool active)
 {
     constexpr int TPL = FftShape<N>::TPL;
-    __syncthreads();
+    lds_barrier();
     if (active) {
 #pragma unroll
         for (int m = 0; m < FftShape<N>::P; ++m) {
@@ -127,7 +127,7 @@ __device__ __forceinline__ void stage_pair(const cT<T> (&u)[FftShape<N>::P], con
             bw[lpad(t + m * TPL)] = w[m];
         }
     }
-    __syncthreads();
+    lds_barrier();
 }
 // LDS slot of the mirror -k (mod N) of position k = t + m TPL
 template <int N> __device__ __forceinline__ int mirror_idx(int t, int m) {

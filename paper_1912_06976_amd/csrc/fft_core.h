@@ -456,6 +456,19 @@ __device__ __forceinline__ cT<T> tw_get_mr(const TableTwiddles<T, N>& tw, int, i
     return tw.p[O + (i - 1) * L + j];
 }
 
+// Block barrier for the LDS exchanges and staging buffers: the fences order
+// the block's LDS accesses only (workgroup scope, local address space), so
+// the barrier waits for this wavefront's LDS operations but not for its
+// global loads in flight -- a prefetch of the next layer or row group keeps
+// running across the exchanges of the current transform (__syncthreads()
+// would wait for it at the first exchange).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Ordering of one wavefront's LDS writes and reads without a block barrier:
 // the LDS executes a wavefront's operations in issue order, so a scheduling
 // barrier between wavefront-scope fences suffices for lanes of one wavefront
@@ -521,12 +534,12 @@ __device__ __forceinline__ void fft_line_p2(cT<T> (&v)[8], cT<T>* __restrict__ l
             constexpr bool WAVE_LOCAL = TPL <= 64;
             const int j = t % L;
             const int base = (t / L) * L * 8 + j;
-            if (!WAVE_LOCAL || s == 0) __syncthreads();
+            if (!WAVE_LOCAL || s == 0) lds_barrier();
             else wave_lds_sync();
 #pragma unroll
             for (int i = 0; i < 8; ++i) lds[lpad(base + i * L)] = v[i];
             if (WAVE_LOCAL) wave_lds_sync();
-            else __syncthreads();
+            else lds_barrier();
 #pragma unroll
             for (int m = 0; m < 8; ++m) v[m] = lds[lpad(t + m * TPL)];
         }
@@ -583,7 +596,7 @@ __device__ __forceinline__ void fft_line_mr(cT<T> (&v)[12], cT<T>* __restrict__ 
             else dft2<T, DIR>(v[u], v[u + NB]);
         }
         if constexpr (s + 1 < NS) {
-            if (!S::WAVE_LOCAL || s == 0) __syncthreads();
+            if (!S::WAVE_LOCAL || s == 0) lds_barrier();
             else wave_lds_sync();
 #pragma unroll
             for (int u = 0; u < NB; ++u) {
@@ -593,7 +606,7 @@ __device__ __forceinline__ void fft_line_mr(cT<T> (&v)[12], cT<T>* __restrict__ 
                 for (int i = 0; i < R; ++i) lds[lpad(base + i * L)] = v[u + i * NB];
             }
             if (S::WAVE_LOCAL) wave_lds_sync();
-            else __syncthreads();
+            else lds_barrier();
 #pragma unroll
             for (int m = 0; m < 12; ++m) v[m] = lds[lpad(t + m * TPL)];
         }

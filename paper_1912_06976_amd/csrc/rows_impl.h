@@ -69,7 +69,7 @@ k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
     const int G = gridDim.x, total = jobs.total;
     const int pr = threadIdx.x / TPL, t = threadIdx.x % TPL;
     TableTwiddles<T, N>::build(lds + C::LDS_R2C, tw, threadIdx.x, C::THREADS);
-    __syncthreads();
+    lds_barrier();
     RowTwiddles<T, N> twl;
     row_twiddles(twl, tw, lds + C::LDS_R2C, threadIdx.x % C::TPL);
     cT<T>* xl = lds + pr * lds_line_elems(N);
@@ -109,10 +109,10 @@ k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
             //   A[k] = (Z[k] + conj Z[N-k]) / 2,  C[k] = (Z[k] - conj Z[N-k]) / (2 i),
             // slot 0 packing the real bins 0 and N/2; element (kx, pair) stores
             // both rows (adjacent in the column) with one 16-byte store
-            __syncthreads();
+            lds_barrier();
 #pragma unroll
             for (int m = 0; m < P; ++m) lds[pr * C::ZR + t + m * TPL] = v[m];
-            __syncthreads();
+            lds_barrier();
 #pragma unroll
             for (int i = 0; i < (C::HALF * C::PAIRS) / C::THREADS; ++i) {
                 const int e = threadIdx.x + i * C::THREADS;
@@ -140,10 +140,10 @@ k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
         } else {
             // split through the line buffer (mirror reads), then stage the
             // half spectra [kx][row] and store the tile
-            __syncthreads();
+            lds_barrier();
 #pragma unroll
             for (int m = 0; m < P; ++m) xl[lpad(t + m * TPL)] = v[m];
-            __syncthreads();
+            lds_barrier();
             cT<T> A[P / 2 + 1], Cc[P / 2 + 1];
 #pragma unroll
             for (int m = 0; m < P / 2 + 1; ++m) {
@@ -159,14 +159,14 @@ k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
                 A[0] = mk<T>(A[0].x, A[P / 2].x);
                 Cc[0] = mk<T>(Cc[0].x, Cc[P / 2].x);
             }
-            __syncthreads();
+            lds_barrier();
 #pragma unroll
             for (int m = 0; m < P / 2; ++m) {
                 const int k = t + m * TPL;
                 lds[k * C::SROW + 2 * pr] = A[m];
                 lds[k * C::SROW + 2 * pr + 1] = Cc[m];
             }
-            __syncthreads();
+            lds_barrier();
 #pragma unroll
             for (int i = 0; i < P; ++i) {
                 const int e = threadIdx.x + i * C::THREADS;   // HALF * RT = P * THREADS
@@ -193,7 +193,7 @@ k_rows_c2r(RowJobs jobs, const cT<T>* __restrict__ tw)
     const int G = gridDim.x, total = jobs.total;
     const int pr = threadIdx.x / TPL, t = threadIdx.x % TPL;
     TableTwiddles<T, N>::build(lds + C::TWO, tw, threadIdx.x, C::THREADS);
-    __syncthreads();
+    lds_barrier();
     RowTwiddlesC2R<T, N> twl;
     row_twiddles(twl, tw, lds + C::TWO, threadIdx.x % C::TPL);
     cT<T>* xl = lds + pr * lds_line_elems(N);
@@ -218,13 +218,13 @@ k_rows_c2r(RowJobs jobs, const cT<T>* __restrict__ tw)
     cT<T> tl[P];
     if (g < total) load(g, tl);
     for (; g < total; g += G) {
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int i = 0; i < P; ++i) {
             const int e = threadIdx.x + i * C::THREADS;
             lds[(e % C::RT) * C::CR + e / C::RT] = tl[i];
         }
-        __syncthreads();
+        lds_barrier();
         if (g + G < total) load(g + G, tl);
         // Z[k] = A[k] + i C[k] over the full length: slot 0 unpacks the real
         // bins 0 and N/2, Hermitian symmetry gives k > N/2
@@ -288,7 +288,7 @@ k_rows_r2c_t(RowJobs jobs, const cT<T>* __restrict__ tw)
     constexpr int LL = lds_line_elems(N);
     __shared__ cT<T> lds[C::LPB * LL + TableTwiddles<T, N>::size()];
     TableTwiddles<T, N>::build(lds + C::LPB * LL, tw, threadIdx.x, C::THREADS);
-    __syncthreads();
+    lds_barrier();
     RowTwiddles<T, N> twl;
     row_twiddles(twl, tw, lds + C::LPB * LL, threadIdx.x % C::TPL);
     const int tl = threadIdx.x / TPL, t = threadIdx.x % TPL;
@@ -320,10 +320,10 @@ k_rows_r2c_t(RowJobs jobs, const cT<T>* __restrict__ tw)
             for (int m = 0; m < P; ++m) v[m] = mk<T>(a[2 * p][m], a[2 * p + 1][m]);
             if (zhi) fft_line<T, N, -1, true>(v, xl, twl, t);
             else fft_line<T, N, -1, false>(v, xl, twl, t);
-            __syncthreads();
+            lds_barrier();
 #pragma unroll
             for (int m = 0; m < P; ++m) xl[lpad(t + m * TPL)] = v[m];
-            __syncthreads();
+            lds_barrier();
 #pragma unroll
             for (int m = 0; m < P / 2 + 1; ++m) {
                 const int k = t + m * TPL;
@@ -367,7 +367,7 @@ k_rows_c2r_t(RowJobs jobs, const cT<T>* __restrict__ tw)
     constexpr int LL = lds_line_elems(N);
     __shared__ cT<T> lds[C::LPB * LL + TableTwiddles<T, N>::size()];
     TableTwiddles<T, N>::build(lds + C::LPB * LL, tw, threadIdx.x, C::THREADS);
-    __syncthreads();
+    lds_barrier();
     RowTwiddlesC2R<T, N> twl;
     row_twiddles(twl, tw, lds + C::LPB * LL, threadIdx.x % C::TPL);
     const int tl = threadIdx.x / TPL, t = threadIdx.x % TPL;
@@ -393,13 +393,13 @@ k_rows_c2r_t(RowJobs jobs, const cT<T>* __restrict__ tw)
         for (int p = 0; p < 4; ++p) {
             // the pair's half spectra A (row 2p) and C (row 2p+1) at k < N/2
             // go through LDS so that each thread can read its mirror positions
-            __syncthreads();
+            lds_barrier();
 #pragma unroll
             for (int m = 0; m < P / 2; ++m) {
                 xl[lpad(t + m * TPL)] = c[m][2 * p];
                 xl[lpad(N / 2 + t + m * TPL)] = c[m][2 * p + 1];
             }
-            __syncthreads();
+            lds_barrier();
             cT<T> v[P];
 #pragma unroll
             for (int m = 0; m < P; ++m) {
