@@ -21,7 +21,10 @@
 // in FP64 and rounded to the working precision.  A per-thread copy of the
 // twiddles each stage needs is held in registers (struct LineTwiddles) so a
 // kernel that transforms many lines of the same length loads them once; the
-// alternative TableTwiddles reads a stage-major copy of them in LDS.
+// alternative TableTwiddles reads a stage-major copy of them in LDS (for the
+// radix-8 stages three powers per butterfly, the other four formed by
+// products), and RegTableTwiddles keeps those three powers in registers.
+// Every twiddle product is rounded the same way whatever the source.
 #pragma once
 #include <hip/hip_runtime.h>
 
