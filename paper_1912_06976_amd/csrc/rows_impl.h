@@ -47,6 +47,11 @@ __device__ __forceinline__ void row_twiddles(TableTwiddles<T, N>& w, const cT<T>
     w.p = tab;
 }
 
+// Power-of-two row kernels load the next group's rows into registers while
+// the current group is transformed. The 2^a 3^b kernels hold more registers
+// per line (radix 12) and run faster loading each group when they reach it.
+template <int N> constexpr bool row_pipe() { return FftShape<N>::POW2; }
+
 // Row kernels are persistent: gridDim.x blocks (about the number that fit on
 // the device at once) walk over the row groups g = lb, lb + G, lb + 2G, ...
 // (lb = XCD-ordered block index, so neighbouring groups, which share 128-byte
@@ -92,10 +97,12 @@ k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
     };
     int g = xcd_order(blockIdx.x, G);
     cT<T> v[P];
-    if (g < total) load(g, v);
+    constexpr bool PIPE = row_pipe<N>();
+    if (PIPE && g < total) load(g, v);
     for (; g < total; g += G) {
         cT<T> vn[P];
-        if (g + G < total) load(g + G, vn);
+        if (!PIPE) load(g, v);
+        if (PIPE && g + G < total) load(g + G, vn);
         const RowJob& J = jobs.j[find_job(jobs, g)];
         const int gl = g - J.begin;
         const int b = gl / J.bpb;
@@ -175,7 +182,8 @@ k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
             }
         }
 #pragma unroll
-        for (int m = 0; m < P; ++m) v[m] = vn[m];
+        for (int m = 0; m < P; ++m)
+            if (PIPE) v[m] = vn[m];
     }
 }
 
@@ -216,8 +224,10 @@ k_rows_c2r(RowJobs jobs, const cT<T>* __restrict__ tw)
     };
     int g = xcd_order(blockIdx.x, G);
     cT<T> tl[P];
-    if (g < total) load(g, tl);
+    constexpr bool PIPE = row_pipe<N>();
+    if (PIPE && g < total) load(g, tl);
     for (; g < total; g += G) {
+        if (!PIPE) load(g, tl);
         lds_barrier();
 #pragma unroll
         for (int i = 0; i < P; ++i) {
@@ -225,7 +235,7 @@ k_rows_c2r(RowJobs jobs, const cT<T>* __restrict__ tw)
             lds[(e % C::RT) * C::CR + e / C::RT] = tl[i];
         }
         lds_barrier();
-        if (g + G < total) load(g + G, tl);
+        if (PIPE && g + G < total) load(g + G, tl);
         // Z[k] = A[k] + i C[k] over the full length: slot 0 unpacks the real
         // bins 0 and N/2, Hermitian symmetry gives k > N/2
         cT<T> v[P];
