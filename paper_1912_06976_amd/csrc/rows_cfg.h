@@ -17,6 +17,18 @@ constexpr int spread_len(int n, int k)
     const int r = 32 / k;
     return n + ((r - n) % 32 + 32) % 32;
 }
+// The same for a tile that a wavefront writes with 8-byte LDS stores as k
+// rows at a few consecutive columns: such stores are conflict-free when each
+// group of sixteen lanes covers sixteen distinct 8-byte slots modulo 16
+// (measured: k = 8 rows at a stride of 2 modulo 16 is conflict-free, at 4
+// modulo 32 half the stores conflict), so the length is congruent to 16 / k
+// modulo 16 (odd for k >= 16).
+constexpr int spread_len_st(int n, int k)
+{
+    if (k >= 16 || n < 16) return n % 2 ? n : n + 1;
+    const int r = 16 / k;
+    return n + ((r - n) % 16 + 16) % 16;
+}
 // P0: pairs of rows per block for long rows (a tuning choice, 2 or 4)
 template <typename T, int N, int P0 = 4> struct RowCfg {
     static constexpr int TPL = FftShape<N>::TPL;
@@ -29,9 +41,9 @@ template <typename T, int N, int P0 = 4> struct RowCfg {
     static constexpr int HALF = N / 2;              // packed half-spectrum columns
     static constexpr int XCH = PAIRS * lds_line_elems(N);
     // c2r: the tile of packed half spectra staged [row][kx], row length CR:
-    // the tile's loads (RT rows of a few kx per wavefront) and the line
+    // the tile's stores (RT rows of a few kx per wavefront) and the line
     // reads (consecutive kx of one row) fall on distinct banks
-    static constexpr int CR = spread_len(HALF, RT);
+    static constexpr int CR = sizeof(T) == 4 ? spread_len_st(HALF, RT) : spread_len(HALF, RT);
     static constexpr int CSTAGE = RT * CR;
     static constexpr int LDS = CSTAGE > XCH ? CSTAGE : XCH;
     static constexpr int TWO = LDS;                 // offset of the LDS twiddle table

@@ -237,21 +237,25 @@ k_rows_c2r(RowJobs jobs, const cT<T>* __restrict__ tw)
         lds_barrier();
         if (PIPE && g + G < total) load(g + G, tl);
         // Z[k] = A[k] + i C[k] over the full length: slot 0 unpacks the real
-        // bins 0 and N/2, Hermitian symmetry gives k > N/2
+        // bins 0 and N/2, Hermitian symmetry gives k > N/2.  Every lane reads
+        // whole elements (the two bins in slot 0 are selected afterwards), so
+        // the reads stay 8-byte accesses of consecutive slots.
         cT<T> v[P];
 #pragma unroll
         for (int m = 0; m < P; ++m) {
             const int k = t + m * TPL;
             const int kk = k <= N / 2 ? k : N - k;
-            cT<T> A, Cc;
-            if (kk == 0 || kk == N / 2) {
-                const cT<T> pa = lds[(2 * pr) * C::CR], pc = lds[(2 * pr + 1) * C::CR];
-                A = mk<T>(kk == 0 ? pa.x : pa.y, 0);
-                Cc = mk<T>(kk == 0 ? pc.x : pc.y, 0);
-            } else {
-                A = lds[(2 * pr) * C::CR + kk];
-                Cc = lds[(2 * pr + 1) * C::CR + kk];
-                if (k > N / 2) { A.y = -A.y; Cc.y = -Cc.y; }
+            const int ks = kk == N / 2 ? 0 : kk;
+            cT<T> A = lds[(2 * pr) * C::CR + ks], Cc = lds[(2 * pr + 1) * C::CR + ks];
+            if (kk == 0) {
+                A.y = 0;
+                Cc.y = 0;
+            } else if (kk == N / 2) {
+                A = mk<T>(A.y, 0);
+                Cc = mk<T>(Cc.y, 0);
+            } else if (k > N / 2) {
+                A.y = -A.y;
+                Cc.y = -Cc.y;
             }
             v[m] = mk<T>(A.x - Cc.y, A.y + Cc.x);
         }
