@@ -473,41 +473,61 @@ k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
     // panel segments share 128-byte lines) run on one XCD
     const int w = xcd_order(blockIdx.x, (int)G);
     const int u0 = (int)((int64_t)w * U / G), u1 = (int)((int64_t)(w + 1) * U / G);
-    // unit u -> (job k, key = cb * nrhs + q, layer l)
-    auto decode = [&](int u, int& k, int& key, int& l) {
-        k = find_job(jobs, u);
-        const int lu = u - jobs.j[k].begin;
-        l = lu % jobs.j[k].nl;
-        key = lu / jobs.j[k].nl;
+    // unit u -> (job k, column block cb, right-hand side q, layer l); a job's
+    // units run layer-fastest, then right-hand side, then column block, so
+    // the walk decodes its first unit and then advances the position (a full
+    // decode again only where the next job begins)
+    struct UPos { int k, cb, q, l; };
+    auto decode = [&](int u) {
+        UPos p;
+        p.k = find_job(jobs, u);
+        const ColJob& J = jobs.j[p.k];
+        const int lu = u - J.begin;
+        const int key = lu / J.nl;
+        p.l = lu - key * J.nl;
+        p.cb = key / J.nrhs;
+        p.q = key - p.cb * J.nrhs;
+        return p;
+    };
+    auto advance = [&](const UPos& p, int un) {   // position of un, the unit after p's
+        if (p.k + 1 < jobs.njobs && un >= jobs.j[p.k + 1].begin) return decode(un);
+        UPos n = p;
+        if (++n.l == jobs.j[p.k].nl) {
+            n.l = 0;
+            if (++n.q == jobs.j[p.k].nrhs) {
+                n.q = 0;
+                ++n.cb;
+            }
+        }
+        return n;
     };
     cT<T> tn[P];
-    auto load_spec = [&](int u) {
-        int k, key, l;
-        decode(u, k, key, l);
-        const ColJob& J = jobs.j[k];
-        const int cb = key / J.nrhs;
-        const int col = cb * C::CPW + cl;
+    auto load_spec = [&](const UPos& p) {
+        const ColJob& J = jobs.j[p.k];
+        const int col = p.cb * C::CPW + cl;
         const int ccol = col < J.ncols ? col : 0;
         if constexpr (SF == FORM_COMPLEX) {
-            const cT<T>* sp = (const cT<T>*)J.spec + ((int64_t)(J.r0 + l) * J.ncols + ccol) * N;
+            const cT<T>* sp = (const cT<T>*)J.spec + ((int64_t)(J.r0 + p.l) * J.ncols + ccol) * N;
 #pragma unroll
             for (int m = 0; m < P; ++m) tn[m] = sp[t + m * TPL];
         } else {
-            load_real_even_c<T, N>(tn, J, J.r0 + l, ccol, cb == 0 && cl == 0, t);
+            load_real_even_c<T, N>(tn, J, J.r0 + p.l, ccol, p.cb == 0 && cl == 0, t);
         }
     };
-    int cur_k = -1, cur_key = -1;
+    int cur_k = -1, cur_cb = -1, cur_q = -1;
     cT<T> rh[P];
     // the 12-point lines have no registers left for the next layer's loads
     // (they would spill): they load each layer when they reach it
     constexpr bool PIPE = FftShape<N>::POW2;
-    if (PIPE && u0 < u1) load_spec(u0);
+    UPos pn{0, 0, 0, 0};
+    if (u0 < u1) pn = decode(u0);
+    if (PIPE && u0 < u1) load_spec(pn);
     for (int u = u0; u < u1; ++u) {
-        if (!PIPE) load_spec(u);
-        int k, key, l;
-        decode(u, k, key, l);
+        const UPos pc = pn;
+        if (u + 1 < u1) pn = advance(pc, u + 1);
+        if (!PIPE) load_spec(pc);
+        const int k = pc.k, l = pc.l, cb = pc.cb, q = pc.q;
         const ColJob& J = jobs.j[k];
-        const int cb = key / J.nrhs, q = key % J.nrhs;
         const int col = cb * C::CPW + cl;
         const bool ok = col < J.ncols;
         const bool packed_blk = cb == 0;
@@ -515,8 +535,8 @@ k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
         cT<T> tv[P];
 #pragma unroll
         for (int m = 0; m < P; ++m) tv[m] = tn[m];
-        if (PIPE && u + 1 < u1) load_spec(u + 1);
-        if (k != cur_k || key != cur_key) {
+        if (PIPE && u + 1 < u1) load_spec(pn);
+        if (k != cur_k || cb != cur_cb || q != cur_q) {
             // R^ of this column: FFT_y of the packed row-pass output of the data
             const cT<T>* rs = (const cT<T>*)J.a + (int64_t)q * J.ncols * J.lda;
 #pragma unroll
@@ -551,7 +571,8 @@ k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
                 }
             }
             cur_k = k;
-            cur_key = key;
+            cur_cb = cb;
+            cur_q = q;
         }
         cT<T> v[P];
         if constexpr (SF == FORM_COMPLEX) {
