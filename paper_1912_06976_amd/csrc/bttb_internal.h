@@ -64,6 +64,7 @@ struct RowJob {
     int nrows;            // rows per batch
     int bpb;              // row groups per batch
     int begin;            // first global row-group index of this job
+    int gq, gr;           // persistent kernels (set at launch): grid / bpb, grid % bpb
 };
 struct RowJobs {
     RowJob j[MAX_JOBS];

@@ -52,6 +52,44 @@ __device__ __forceinline__ void row_twiddles(TableTwiddles<T, N>& w, const cT<T>
 // per line (radix 12) and run faster loading each group when they reach it.
 template <int N> constexpr bool row_pipe() { return FftShape<N>::POW2; }
 
+// Position of row group g of a job table: job k, batch b, group rg of the
+// batch.  A persistent block visits g, g + G, g + 2G, ...: it decodes its
+// first group and then advances by the job's gq = G / bpb batches and
+// gr = G % bpb groups (set at launch), decoding again only where the step
+// enters another job.
+struct RowPos { int k, b, rg; };
+__device__ __forceinline__ RowPos row_pos(const RowJobs& js, int g)
+{
+    RowPos p;
+    p.k = find_job(js, g);
+    const RowJob& J = js.j[p.k];
+    const int gl = g - J.begin;
+    p.b = gl / J.bpb;
+    p.rg = gl - p.b * J.bpb;
+    return p;
+}
+__device__ __forceinline__ RowPos row_pos_next(const RowJobs& js, const RowPos& p, int gn)
+{
+    if (p.k + 1 < js.njobs && gn >= js.j[p.k + 1].begin) return row_pos(js, gn);
+    const RowJob& J = js.j[p.k];
+    RowPos n{p.k, p.b + J.gq, p.rg + J.gr};
+    if (n.rg >= J.bpb) {
+        n.rg -= J.bpb;
+        ++n.b;
+    }
+    return n;
+}
+// The host side of it: the table as launched on a grid of G blocks.
+static inline RowJobs rows_for_grid(const RowJobs& jobs, int G)
+{
+    RowJobs js = jobs;
+    for (int i = 0; i < js.njobs; ++i) {
+        js.j[i].gq = G / js.j[i].bpb;
+        js.j[i].gr = G % js.j[i].bpb;
+    }
+    return js;
+}
+
 // Row kernels are persistent: gridDim.x blocks (about the number that fit on
 // the device at once) walk over the row groups g = lb, lb + G, lb + 2G, ...
 // (lb = XCD-ordered block index, so neighbouring groups, which share 128-byte
@@ -78,12 +116,10 @@ k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
     RowTwiddles<T, N> twl;
     row_twiddles(twl, tw, lds + C::LDS_R2C, threadIdx.x % C::TPL);
     cT<T>* xl = lds + pr * lds_line_elems(N);
-    auto load = [&](int g, cT<T> (&v)[P]) {
-        const RowJob& J = jobs.j[find_job(jobs, g)];
-        const int gl = g - J.begin;
-        const int b = gl / J.bpb;
-        const int ra = (gl % J.bpb) * C::RT + 2 * pr, rb = ra + 1;
-        const TI* src = (const TI*)J.in + (int64_t)b * J.in_bs;
+    auto load = [&](const RowPos& p, cT<T> (&v)[P]) {
+        const RowJob& J = jobs.j[p.k];
+        const int ra = p.rg * C::RT + 2 * pr, rb = ra + 1;
+        const TI* src = (const TI*)J.in + (int64_t)p.b * J.in_bs;
 #pragma unroll
         for (int m = 0; m < P; ++m) {
             const int x = t + m * TPL;
@@ -98,15 +134,17 @@ k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
     int g = xcd_order(blockIdx.x, G);
     cT<T> v[P];
     constexpr bool PIPE = row_pipe<N>();
-    if (PIPE && g < total) load(g, v);
+    RowPos pn = row_pos(jobs, g < total ? g : 0);
+    if (PIPE && g < total) load(pn, v);
     for (; g < total; g += G) {
+        const RowPos pc = pn;
+        if (g + G < total) pn = row_pos_next(jobs, pc, g + G);
         cT<T> vn[P];
-        if (!PIPE) load(g, v);
-        if (PIPE && g + G < total) load(g + G, vn);
-        const RowJob& J = jobs.j[find_job(jobs, g)];
-        const int gl = g - J.begin;
-        const int b = gl / J.bpb;
-        const int row0 = (gl % J.bpb) * C::RT;
+        if (!PIPE) load(pc, v);
+        if (PIPE && g + G < total) load(pn, vn);
+        const RowJob& J = jobs.j[pc.k];
+        const int b = pc.b;
+        const int row0 = pc.rg * C::RT;
         if (J.nv <= N / 2) fft_line<T, N, -1, true>(v, xl, twl, t);
         else fft_line<T, N, -1, false>(v, xl, twl, t);
         cT<T>* dst = (cT<T>*)J.out + (int64_t)b * J.out_bs;
@@ -209,12 +247,10 @@ k_rows_c2r(RowJobs jobs, const cT<T>* __restrict__ tw)
     // elements, element e = threadIdx.x + i THREADS at (kx, row) = (e / RT, e % RT)
     // (8-byte loads: eight lanes per 64-byte column segment; 16-byte loads,
     // with twice the segments per instruction, measured slower)
-    auto load = [&](int g, cT<T> (&tl)[P]) {
-        const RowJob& J = jobs.j[find_job(jobs, g)];
-        const int gl = g - J.begin;
-        const int b = gl / J.bpb;
-        const int row0 = (gl % J.bpb) * C::RT;
-        const cT<T>* src = (const cT<T>*)J.in + (int64_t)b * J.in_bs;
+    auto load = [&](const RowPos& p, cT<T> (&tl)[P]) {
+        const RowJob& J = jobs.j[p.k];
+        const int row0 = p.rg * C::RT;
+        const cT<T>* src = (const cT<T>*)J.in + (int64_t)p.b * J.in_bs;
 #pragma unroll
         for (int i = 0; i < P; ++i) {
             const int e = threadIdx.x + i * C::THREADS;
@@ -225,9 +261,12 @@ k_rows_c2r(RowJobs jobs, const cT<T>* __restrict__ tw)
     int g = xcd_order(blockIdx.x, G);
     cT<T> tl[P];
     constexpr bool PIPE = row_pipe<N>();
-    if (PIPE && g < total) load(g, tl);
+    RowPos pn = row_pos(jobs, g < total ? g : 0);
+    if (PIPE && g < total) load(pn, tl);
     for (; g < total; g += G) {
-        if (!PIPE) load(g, tl);
+        const RowPos pc = pn;
+        if (g + G < total) pn = row_pos_next(jobs, pc, g + G);
+        if (!PIPE) load(pc, tl);
         lds_barrier();
 #pragma unroll
         for (int i = 0; i < P; ++i) {
@@ -235,7 +274,7 @@ k_rows_c2r(RowJobs jobs, const cT<T>* __restrict__ tw)
             lds[(e % C::RT) * C::CR + e / C::RT] = tl[i];
         }
         lds_barrier();
-        if (PIPE && g + G < total) load(g + G, tl);
+        if (PIPE && g + G < total) load(pn, tl);
         // Z[k] = A[k] + i C[k] over the full length: slot 0 unpacks the real
         // bins 0 and N/2, Hermitian symmetry gives k > N/2.  Every lane reads
         // whole elements (the two bins in slot 0 are selected afterwards), so
@@ -260,11 +299,9 @@ k_rows_c2r(RowJobs jobs, const cT<T>* __restrict__ tw)
             v[m] = mk<T>(A.x - Cc.y, A.y + Cc.x);
         }
         fft_line<T, N, +1, false>(v, xl, twl, t);   // begins with a barrier
-        const RowJob& J = jobs.j[find_job(jobs, g)];
-        const int gl = g - J.begin;
-        const int b = gl / J.bpb;
-        const int ra = (gl % J.bpb) * C::RT + 2 * pr, rb = ra + 1;
-        T* dst = (T*)J.out + (int64_t)b * J.out_bs;
+        const RowJob& J = jobs.j[pc.k];
+        const int ra = pc.rg * C::RT + 2 * pr, rb = ra + 1;
+        T* dst = (T*)J.out + (int64_t)pc.b * J.out_bs;
 #pragma unroll
         for (int m = 0; m < P; ++m) {
             const int x = t + m * TPL;
@@ -505,8 +542,8 @@ static hipError_t launch_r2c_n(const RowJobs& jobs, const cT<T>* tw, hipStream_t
     using C = RowCfg<T, NN, P0>;
     // thread-safe one-time initialisation (function-local static)
     static const int resident = resident_blocks((const void*)k_rows_r2c<TI, T, NN, P0>, C::THREADS);
-    hipLaunchKernelGGL((k_rows_r2c<TI, T, NN, P0>), dim3(std::min(jobs.total, resident)), dim3(C::THREADS), 0, s,
-                       jobs, tw);
+    const int G = std::min(jobs.total, resident);
+    hipLaunchKernelGGL((k_rows_r2c<TI, T, NN, P0>), dim3(G), dim3(C::THREADS), 0, s, rows_for_grid(jobs, G), tw);
     return hipGetLastError();
 }
 
@@ -516,8 +553,8 @@ static hipError_t launch_c2r_n(const RowJobs& jobs, const cT<T>* tw, hipStream_t
     using C = RowCfg<T, NN, P0>;
     // thread-safe one-time initialisation (function-local static)
     static const int resident = resident_blocks((const void*)k_rows_c2r<T, NN, P0>, C::THREADS);
-    hipLaunchKernelGGL((k_rows_c2r<T, NN, P0>), dim3(std::min(jobs.total, resident)), dim3(C::THREADS), 0, s,
-                       jobs, tw);
+    const int G = std::min(jobs.total, resident);
+    hipLaunchKernelGGL((k_rows_c2r<T, NN, P0>), dim3(G), dim3(C::THREADS), 0, s, rows_for_grid(jobs, G), tw);
     return hipGetLastError();
 }
 
