@@ -395,6 +395,15 @@ bttb_status bttb_transpose_profiled(bttb_plan_t plan, const void* spectra, const
 bttb_status bttb_debug_generator(bttb_plan_t plan, int32_t layer, double* host_out,
                                  void* workspace, size_t ws_bytes, void* stream);
 
+/* Test hook: cap the grid of the persistent kernels (the row transforms and
+ * the transpose multiply-accumulate, which size their grids to the blocks
+ * resident at once and walk the work units) at max_blocks blocks, for every
+ * launch this process makes afterwards (graphs already captured keep their
+ * grids); 0 restores the default.  Each block then walks more units; the
+ * results are the same bit for bit.  Not for use while other threads launch.
+ * Errors: INVALID_VALUE (max_blocks < 0). */
+bttb_status bttb_debug_cap_grid(int32_t max_blocks);
+
 /* Static description of a status code. */
 const char* bttb_status_string(bttb_status s);
 

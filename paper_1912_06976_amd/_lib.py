@@ -22,7 +22,7 @@ NOALLOC_SCRATCH_BYTES = 64 << 20
 #: every symbol include/bttb.h declares
 EXPORTS = ["bttb_plan_create", "bttb_plan_destroy", "bttb_plan_query", "bttb_plan_memory_check", "bttb_kernel_generate",
            "bttb_forward", "bttb_transpose", "bttb_forward_noalloc", "bttb_forward_profiled",
-           "bttb_transpose_profiled", "bttb_debug_generator", "bttb_plan_spectrum_form", "bttb_kernel_generate_table", "bttb_cgls_query", "bttb_cgls", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
+           "bttb_transpose_profiled", "bttb_debug_generator", "bttb_debug_cap_grid", "bttb_plan_spectrum_form", "bttb_kernel_generate_table", "bttb_cgls_query", "bttb_cgls", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
            "bttb_batch_destroy", "bttb_autotune_query", "bttb_autotune", "bttb_status_string",
            "bttb_last_error"]
 
@@ -82,6 +82,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     L.bttb_forward_profiled.argtypes = [vp, vp, vp, vp, i32, vp, sz, vp, ctypes.POINTER(ctypes.c_float)]
     L.bttb_transpose_profiled.argtypes = [vp, vp, vp, vp, i32, vp, sz, vp, ctypes.POINTER(ctypes.c_float)]
     L.bttb_debug_generator.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), vp, sz, vp]
+    L.bttb_debug_cap_grid.argtypes = [i32]
     L.bttb_plan_spectrum_form.argtypes = [vp, ctypes.POINTER(i32)]
     L.bttb_kernel_generate_table.argtypes = [vp, vp, vp, vp, sz, vp]
     L.bttb_cgls_query.argtypes = [vp, ctypes.POINTER(sz)]
@@ -100,7 +101,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     for name in ["bttb_plan_create", "bttb_plan_destroy", "bttb_plan_query", "bttb_plan_memory_check",
                  "bttb_kernel_generate",
                  "bttb_forward", "bttb_transpose", "bttb_forward_noalloc", "bttb_forward_profiled",
-                 "bttb_transpose_profiled", "bttb_debug_generator", "bttb_plan_spectrum_form", "bttb_kernel_generate_table", "bttb_cgls_query", "bttb_cgls", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
+                 "bttb_transpose_profiled", "bttb_debug_generator", "bttb_debug_cap_grid", "bttb_plan_spectrum_form", "bttb_kernel_generate_table", "bttb_cgls_query", "bttb_cgls", "bttb_batch_create", "bttb_batch_query", "bttb_batch_run",
                  "bttb_batch_destroy", "bttb_autotune_query", "bttb_autotune"]:
         getattr(L, name).restype = ctypes.c_int
     _handle = L

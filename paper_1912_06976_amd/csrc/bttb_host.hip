@@ -1093,6 +1093,14 @@ bttb_status bttb_plan_spectrum_form(bttb_plan_t plan, int32_t* form)
     return BTTB_OK;
 }
 
+bttb_status bttb_debug_cap_grid(int32_t max_blocks)
+{
+    g_last_error.clear();
+    if (max_blocks < 0) return fail(BTTB_ERR_INVALID_VALUE, "max_blocks must be >= 0");
+    g_persistent_grid_cap.store(max_blocks, std::memory_order_relaxed);
+    return BTTB_OK;
+}
+
 bttb_status bttb_debug_generator(bttb_plan_t plan, int32_t layer, double* host_out, void* workspace,
                                  size_t ws_bytes, void* stream)
 {

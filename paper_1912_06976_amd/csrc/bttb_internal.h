@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 namespace bttbk {
 
 enum { KIND_GRAVITY = 0, KIND_MAGNETIC = 1, KIND_TABLE = 2, KIND_PROBE = 99 };
@@ -14,6 +16,11 @@ enum { FORM_COMPLEX = 0, FORM_REAL_EVEN = 1 };
 struct MagWeights { double g[5]; };
 
 constexpr int MAX_GEN_BATCH = 8;   // layers per generator launch
+
+// Test hook (bttb_debug_cap_grid): an upper bound on the grid of the
+// persistent kernels, 0 for none.  A smaller grid makes every block walk more
+// work units; the results do not depend on the grid.
+inline std::atomic<int> g_persistent_grid_cap{0};
 
 struct GenParams {
     int kind;

@@ -667,7 +667,7 @@ static void launch_tr_k(const ColJobs& jobs, const cT<T>* tw, hipStream_t s)
 {
     // thread-safe one-time initialisation (function-local static)
     static const int resident = resident_blocks((const void*)k_cols_tr_mac<T, NN, 1, CM, SF>, ColCfg<NN, CM>::THREADS);
-    hipLaunchKernelGGL((k_cols_tr_mac<T, NN, 1, CM, SF>), dim3(std::min(jobs.total, resident)),
+    hipLaunchKernelGGL((k_cols_tr_mac<T, NN, 1, CM, SF>), dim3(persistent_grid(jobs.total, resident)),
                        dim3(ColCfg<NN, CM>::THREADS), 0, s, jobs, tw);
 }
 template <typename T, int NN>

@@ -95,6 +95,15 @@ template <typename T, int NN> constexpr bool col_tile2_fits()
     case 3072: MACRO(3072); break;\
     default: return hipErrorInvalidValue; }
 
+// grid of a persistent launch over `total` work units (at most the blocks
+// resident at once, and at most the test hook's cap when one is set)
+static inline int persistent_grid(int total, int resident)
+{
+    const int cap = g_persistent_grid_cap.load(std::memory_order_relaxed);
+    const int g = std::min(total, resident);
+    return cap > 0 && cap < g ? cap : g;
+}
+
 // blocks of `kernel` that are resident on the whole current device at once
 // (occupancy per CU times the number of CUs); at least 1
 static inline int resident_blocks(const void* kernel, int threads)

@@ -542,7 +542,7 @@ static hipError_t launch_r2c_n(const RowJobs& jobs, const cT<T>* tw, hipStream_t
     using C = RowCfg<T, NN, P0>;
     // thread-safe one-time initialisation (function-local static)
     static const int resident = resident_blocks((const void*)k_rows_r2c<TI, T, NN, P0>, C::THREADS);
-    const int G = std::min(jobs.total, resident);
+    const int G = persistent_grid(jobs.total, resident);
     hipLaunchKernelGGL((k_rows_r2c<TI, T, NN, P0>), dim3(G), dim3(C::THREADS), 0, s, rows_for_grid(jobs, G), tw);
     return hipGetLastError();
 }
@@ -553,7 +553,7 @@ static hipError_t launch_c2r_n(const RowJobs& jobs, const cT<T>* tw, hipStream_t
     using C = RowCfg<T, NN, P0>;
     // thread-safe one-time initialisation (function-local static)
     static const int resident = resident_blocks((const void*)k_rows_c2r<T, NN, P0>, C::THREADS);
-    const int G = std::min(jobs.total, resident);
+    const int G = persistent_grid(jobs.total, resident);
     hipLaunchKernelGGL((k_rows_c2r<T, NN, P0>), dim3(G), dim3(C::THREADS), 0, s, rows_for_grid(jobs, G), tw);
     return hipGetLastError();
 }
@@ -565,7 +565,7 @@ static hipError_t launch_r2c_t(const RowJobs& jobs, const cT<T>* tw, hipStream_t
     // thread-safe one-time initialisation (function-local static)
     static const int resident = resident_blocks((const void*)k_rows_r2c_t<TI, T, NN>, C::THREADS);
     const int nb = (jobs.total + C::LPB - 1) / C::LPB;
-    hipLaunchKernelGGL((k_rows_r2c_t<TI, T, NN>), dim3(std::min(nb, resident)), dim3(C::THREADS), 0, s, jobs, tw);
+    hipLaunchKernelGGL((k_rows_r2c_t<TI, T, NN>), dim3(persistent_grid(nb, resident)), dim3(C::THREADS), 0, s, jobs, tw);
     return hipGetLastError();
 }
 
@@ -576,7 +576,7 @@ static hipError_t launch_c2r_t(const RowJobs& jobs, const cT<T>* tw, hipStream_t
     // thread-safe one-time initialisation (function-local static)
     static const int resident = resident_blocks((const void*)k_rows_c2r_t<T, NN>, C::THREADS);
     const int nb = (jobs.total + C::LPB - 1) / C::LPB;
-    hipLaunchKernelGGL((k_rows_c2r_t<T, NN>), dim3(std::min(nb, resident)), dim3(C::THREADS), 0, s, jobs, tw);
+    hipLaunchKernelGGL((k_rows_c2r_t<T, NN>), dim3(persistent_grid(nb, resident)), dim3(C::THREADS), 0, s, jobs, tw);
     return hipGetLastError();
 }
 

@@ -226,6 +226,10 @@ def bttb_cgls(plan: int, spectra: torch.Tensor, d: torch.Tensor, m: torch.Tensor
                                 _stream_ptr(stream)))
 
 
+def bttb_debug_cap_grid(max_blocks: int) -> None:
+    check("bttb_debug_cap_grid", _lib.load().bttb_debug_cap_grid(max_blocks))
+
+
 def bttb_debug_generator(plan: int, layer: int, workspace: torch.Tensor, stream=None) -> np.ndarray:
     _, _, nx, ny = bttb_plan_query(plan, 1)
     out = np.empty((ny, nx), dtype=np.float64)

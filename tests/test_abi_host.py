@@ -312,3 +312,11 @@ def test_hessian_descriptor_checks(lib):
         h = B.bttb_plan_create(dict(base, hessian=w), "fp32")
         assert B.bttb_plan_spectrum_form(h) == form, w
         B.bttb_plan_destroy(h)
+
+
+def test_grid_cap_hook_checks(lib):
+    # host state only: no launch
+    assert lib.bttb_debug_cap_grid(-1) == 1
+    assert "max_blocks" in lib.bttb_last_error().decode()
+    assert lib.bttb_debug_cap_grid(5) == 0
+    assert lib.bttb_debug_cap_grid(0) == 0
