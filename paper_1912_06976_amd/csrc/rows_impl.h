@@ -84,8 +84,9 @@ static inline RowJobs rows_for_grid(const RowJobs& jobs, int G)
 {
     RowJobs js = jobs;
     for (int i = 0; i < js.njobs; ++i) {
-        js.j[i].gq = G / js.j[i].bpb;
-        js.j[i].gr = G % js.j[i].bpb;
+        const int bpb = js.j[i].bpb > 0 ? js.j[i].bpb : 1;   // a job has >= 1 row
+        js.j[i].gq = G / bpb;
+        js.j[i].gr = G % bpb;
     }
     return js;
 }
