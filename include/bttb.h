@@ -284,6 +284,11 @@ bttb_status bttb_forward_noalloc(bttb_plan_t plan, const void* spectra, const vo
  *   q = G p,  alpha = gamma / (||q||^2 + lambda^2 ||p||^2),
  *   m += alpha p,  r -= alpha q,  s = G^T r - lambda^2 m,
  *   beta = ||s||^2 / gamma,  p = s + beta p.
+ * Once ||s_k|| <= tau ||s_0|| (tau = 1e-6 for FP32 plans, 1e-12 for FP64)
+ * the remaining steps leave m unchanged (alpha = 0; the history repeats):
+ * the products are each other's adjoint only to their rounding, and
+ * conjugate gradients iterated far below that level can drift away from
+ * the solution.
  * Every step runs on the device (the product kernels plus FP64-accumulating
  * vector kernels); scalars stay on the device, so the call does not
  * synchronise and can be captured in a graph.

@@ -193,16 +193,19 @@ __global__ void __launch_bounds__(RED_THREADS) k_step(T* __restrict__ r, const T
     if (threadIdx.x == 0) out[blockIdx.x] = a;
 }
 
-// alpha = gamma / (||q||^2 + lambda^2 ||p||^2) (0 when the denominator is 0)
+// alpha = gamma / (||q||^2 + lambda^2 ||p||^2); 0 when the denominator is 0
+// or once the gradient has converged, gamma <= tol2 gamma0: from there on the
+// steps leave m and r as they are
 __global__ void __launch_bounds__(RED_THREADS) k_alpha(const double* __restrict__ pq, const double* __restrict__ pp,
-                                                       int nb, double lam2, CglsScalars* __restrict__ sc)
+                                                       int nb, double lam2, double tol2, CglsScalars* __restrict__ sc)
 {
     const double qq = sum_partials(pq, nb);
     __syncthreads();
     const double ppv = sum_partials(pp, nb);
     if (threadIdx.x == 0) {
         const double den = qq + lam2 * ppv;
-        sc->alpha = den > 0.0 ? sc->gamma / den : 0.0;
+        const bool converged = sc->gamma <= tol2 * sc->gamma0;
+        sc->alpha = den > 0.0 && !converged ? sc->gamma / den : 0.0;
     }
 }
 
@@ -220,6 +223,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_beta(const double* __restrict__
     if (threadIdx.x == 0) {
         sc->beta = (!first && sc->gamma > 0.0) ? ss / sc->gamma : 0.0;
         sc->gamma = ss;
+        if (first) sc->gamma0 = ss;
         if (hist) {
             hist[3 * k] = rr;
             hist[3 * k + 1] = mm;
@@ -261,9 +265,10 @@ hipError_t launch_cgls_step(T* r, const T* q, int64_t nd, const CglsScalars* sc,
     hipLaunchKernelGGL(k_step<T>, dim3(nb), dim3(RED_THREADS), 0, s, r, q, nd, sc, out);
     return hipGetLastError();
 }
-hipError_t launch_cgls_alpha(const double* pq, const double* pp, int nb, double lam2, CglsScalars* sc, hipStream_t s)
+hipError_t launch_cgls_alpha(const double* pq, const double* pp, int nb, double lam2, double tol2, CglsScalars* sc,
+                             hipStream_t s)
 {
-    hipLaunchKernelGGL(k_alpha, dim3(1), dim3(RED_THREADS), 0, s, pq, pp, nb, lam2, sc);
+    hipLaunchKernelGGL(k_alpha, dim3(1), dim3(RED_THREADS), 0, s, pq, pp, nb, lam2, tol2, sc);
     return hipGetLastError();
 }
 hipError_t launch_cgls_beta(const double* ps, const double* pr, const double* pm, int nb, CglsScalars* sc,

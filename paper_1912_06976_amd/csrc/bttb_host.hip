@@ -721,6 +721,11 @@ CglsLayout cgls_layout(const bttb_plan_s* P)
 //   q = G p; alpha = gamma / (||q||^2 + lambda^2 ||p||^2);
 //   m += alpha p; r -= alpha q; s = G^T r - lambda^2 m;
 //   beta = ||s||^2 / gamma; p = s + beta p
+// with alpha = 0 once ||s_k|| <= tol ||s_0||.  The products are adjoint only
+// to their rounding (FP32: about 1e-7), and conjugate gradients on the then
+// slightly non-symmetric normal operator can drift away from the solution
+// when iterated far below that level; the tolerance stops them above it.
+constexpr double CGLS_TOL_FP32 = 1e-6, CGLS_TOL_FP64 = 1e-12;
 template <typename T>
 bttb_status run_cgls(const bttb_plan_s* P, const char* spec, const T* d, T* m, double lam, int iters, double* hist,
                      char* ws, hipStream_t st)
@@ -735,6 +740,7 @@ bttb_status run_cgls(const bttb_plan_s* P, const char* spec, const T* d, T* m, d
     double *pq = part, *pp = part + L.nb, *ps = part + 2 * L.nb, *pr = part + 3 * L.nb, *pm = part + 4 * L.nb;
     CglsScalars* sc = (CglsScalars*)(ws + L.scal);
     const double lam2 = lam * lam;
+    const double tol = sizeof(T) == 4 ? CGLS_TOL_FP32 : CGLS_TOL_FP64;
     const int nb = L.nb;
     bttb_status e;
 #define CG(x, what) if ((e = (x)) != BTTB_OK) return e
@@ -748,7 +754,7 @@ bttb_status run_cgls(const bttb_plan_s* P, const char* spec, const T* d, T* m, d
     for (int k = 1; k <= iters; ++k) {
         CG(run_single<T>(true, P, spec, p, q, 1, wp, st), "forward");
         CGH(launch_cgls_dot<T>(q, q, L.nd, pq, nb, st), "cgls dot");
-        CGH(launch_cgls_alpha(pq, pp, nb, lam2, sc, st), "cgls scalars");
+        CGH(launch_cgls_alpha(pq, pp, nb, lam2, tol * tol, sc, st), "cgls scalars");
         CGH(launch_cgls_step<T>(r, q, L.nd, sc, pr, nb, st), "cgls step");
         CG(run_single<T>(false, P, spec, r, sv, 1, wp, st), "transpose");
         // m += alpha p with s = G^T r - lambda^2 m (one pass over m, p, s)

@@ -101,7 +101,7 @@ struct ColJobs {
 };
 
 // device scalars of the CGLS iteration
-struct CglsScalars { double gamma, alpha, beta, pad; };
+struct CglsScalars { double gamma, alpha, beta, gamma0; };   // gamma0 = ||s_0||^2
 
 template <typename T> struct cplx;
 template <> struct cplx<float> { using type = float2; };
@@ -151,7 +151,8 @@ hipError_t launch_cgls_direction(const T* sv, T* p, int64_t n, const CglsScalars
                                  hipStream_t s);
 template <typename T>
 hipError_t launch_cgls_step(T* r, const T* q, int64_t nd, const CglsScalars* sc, double* out, int nb, hipStream_t s);
-hipError_t launch_cgls_alpha(const double* pq, const double* pp, int nb, double lam2, CglsScalars* sc, hipStream_t s);
+hipError_t launch_cgls_alpha(const double* pq, const double* pp, int nb, double lam2, double tol2, CglsScalars* sc,
+                             hipStream_t s);
 hipError_t launch_cgls_beta(const double* ps, const double* pr, const double* pm, int nb, CglsScalars* sc,
                             double* hist, int k, int first, hipStream_t s);
 

@@ -60,6 +60,37 @@ def test_cgls_converges_to_dense_regularized_solution(torch_cuda, name, prec, to
     assert abs(J[-1] - Jref) <= (1e-10 if prec == "fp64" else 1e-5) * Jref
 
 
+@pytest.mark.parametrize("name,prec,tol", [("magnetic_24", "fp32", 2e-4), ("small_gravity", "fp32", 2e-4),
+                                           ("magnetic_24", "fp64", 1e-9)])
+def test_cgls_holds_the_solution_after_convergence(torch_cuda, name, prec, tol):
+    """Many more steps than convergence needs: once ||s_k|| <= tau ||s_0||
+    (tau = 1e-6 FP32, 1e-12 FP64) the steps leave m unchanged, so the
+    iterate stays at the solution instead of drifting (in FP32 the products
+    are each other's adjoint only to rounding); 150 and 600 steps then end
+    on the same iterate, bit for bit, and the history repeats its last row."""
+    import oracle
+    from paper_1912_06976_amd import Plan
+    torch = torch_cuda
+    pr = getattr(W, name)()
+    print("cgls long", name, prec, flush=True)
+    G, d, sv = _case(pr, 61)
+    lam = 0.1 * sv[0]
+    ref = oracle.regularized_lsq(G, d, lam)
+    plan = Plan(pr, prec).generate()
+    dt = torch.tensor(d.reshape(pr["sy"], pr["sx"]), dtype=plan.dtype, device="cuda")
+    tau = 1e-6 if prec == "fp32" else 1e-12
+    m150, _ = plan.cgls(dt, lam, 150)
+    m600, h = plan.cgls(dt, lam, 600)
+    torch.cuda.synchronize()
+    h = h.cpu().numpy()
+    stop = int(np.argmax(h[:, 2] <= tau * tau * h[0, 2]))
+    assert h[stop, 2] <= tau * tau * h[0, 2] and 0 < stop < 150, stop
+    assert np.array_equal(h[stop:], np.broadcast_to(h[stop], h[stop:].shape))
+    assert torch.equal(m150, m600)
+    got = m600.double().cpu().numpy().ravel()
+    assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref), np.linalg.norm(got - ref) / np.linalg.norm(ref)
+
+
 def test_cgls_warm_start_zero_steps_and_validation(torch_cuda):
     import paper_1912_06976_amd as B
     from paper_1912_06976_amd import Plan
