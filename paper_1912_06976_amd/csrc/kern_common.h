@@ -95,6 +95,34 @@ template <typename T, int NN> constexpr bool col_tile2_fits()
     case 3072: MACRO(3072); break;\
     default: return hipErrorInvalidValue; }
 
+// Stores through a raw buffer resource over [base, base + bytes).  The
+// hardware drops a buffer store whose byte offset lies at or past the
+// resource's size, so a lane that must not store is given an offset with
+// bit 31 set (every size stays below 2^31) and the store needs no branch.
+// With no stores skipped by branches the compiler knows how many memory
+// operations were issued after a prefetch, and waits for the prefetch alone
+// instead of draining the stores with it.
+constexpr uint32_t BUF_SKIP = 0x80000000u;
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(void* base, uint32_t bytes)
+{
+    // descriptor word 3 for raw (unformatted) access on gfx9-family targets
+    return __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)bytes, 0x00020000);
+}
+template <typename V> __device__ __forceinline__ void buf_store(const V& v, __amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    if constexpr (sizeof(V) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0, 0);
+    else if constexpr (sizeof(V) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, (int)off, 0, 0);
+    else {
+        static_assert(sizeof(V) == 16, "4, 8 or 16 bytes");
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), r, (int)off, 0, 0);
+    }
+}
+constexpr int64_t BUF_MAX_BYTES = int64_t(1) << 31;
+
 // grid of a persistent launch over `total` work units (at most the blocks
 // resident at once, and at most the test hook's cap when one is set)
 static inline int persistent_grid(int total, int resident)

@@ -302,14 +302,18 @@ k_rows_c2r(RowJobs jobs, const cT<T>* __restrict__ tw)
         fft_line<T, N, +1, false>(v, xl, twl, t);   // begins with a barrier
         const RowJob& J = jobs.j[pc.k];
         const int ra = pc.rg * C::RT + 2 * pr, rb = ra + 1;
-        T* dst = (T*)J.out + (int64_t)pc.b * J.out_bs;
+        // buffer stores (no branches; the launcher checks the sizes)
+        const auto rs = buf_rsrc((T*)J.out + (int64_t)pc.b * J.out_bs,
+                                 (uint32_t)((int64_t)J.nrows * J.out_ld * (int64_t)sizeof(T)));
+        const uint32_t ska = ra < J.nrows ? 0u : BUF_SKIP, skb = rb < J.nrows ? 0u : BUF_SKIP;
+        const uint32_t oa0 = (uint32_t)((int64_t)ra * J.out_ld * (int64_t)sizeof(T));
+        const uint32_t ld = (uint32_t)(J.out_ld * (int64_t)sizeof(T));
 #pragma unroll
         for (int m = 0; m < P; ++m) {
             const int x = t + m * TPL;
-            if (x < J.nv) {
-                if (ra < J.nrows) dst[(int64_t)ra * J.out_ld + x] = v[m].x;
-                if (rb < J.nrows) dst[(int64_t)rb * J.out_ld + x] = v[m].y;
-            }
+            const uint32_t oa = oa0 + (uint32_t)x * (uint32_t)sizeof(T), skx = x < J.nv ? 0u : BUF_SKIP;
+            buf_store(v[m].x, rs, oa | ska | skx);
+            buf_store(v[m].y, rs, (oa + ld) | skb | skx);
         }
     }
 }
@@ -554,6 +558,11 @@ static hipError_t launch_c2r_n(const RowJobs& jobs, const cT<T>* tw, hipStream_t
     using C = RowCfg<T, NN, P0>;
     // thread-safe one-time initialisation (function-local static)
     static const int resident = resident_blocks((const void*)k_rows_c2r<T, NN, P0>, C::THREADS);
+    // the kernel's buffer stores address a batch's rows (and the rows of a
+    // partial last group) with 32-bit byte offsets below 2^31
+    for (int i = 0; i < jobs.njobs; ++i)
+        if ((int64_t)(jobs.j[i].nrows + C::RT) * jobs.j[i].out_ld * (int64_t)sizeof(T) >= BUF_MAX_BYTES)
+            return hipErrorInvalidValue;
     const int G = persistent_grid(jobs.total, resident);
     hipLaunchKernelGGL((k_rows_c2r<T, NN, P0>), dim3(G), dim3(C::THREADS), 0, s, rows_for_grid(jobs, G), tw);
     return hipGetLastError();
