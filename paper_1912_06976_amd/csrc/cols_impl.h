@@ -521,20 +521,27 @@ k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
     constexpr bool PIPE = FftShape<N>::POW2;
     UPos pn{0, 0, 0, 0};
     if (u0 < u1) pn = decode(u0);
-    if (PIPE && u0 < u1) load_spec(pn);
+    // tv: this unit's spectra (from tn, the prefetch registers)
+    cT<T> tv[P];
+    if (PIPE && u0 < u1) {
+        load_spec(pn);
+#pragma unroll
+        for (int m = 0; m < P; ++m) tv[m] = tn[m];
+    }
     for (int u = u0; u < u1; ++u) {
         const UPos pc = pn;
         if (u + 1 < u1) pn = advance(pc, u + 1);
-        if (!PIPE) load_spec(pc);
+        if (!PIPE) {
+            load_spec(pc);
+#pragma unroll
+            for (int m = 0; m < P; ++m) tv[m] = tn[m];
+        }
         const int k = pc.k, l = pc.l, cb = pc.cb, q = pc.q;
         const ColJob& J = jobs.j[k];
         const int col = cb * C::CPW + cl;
         const bool ok = col < J.ncols;
         const bool packed_blk = cb == 0;
         const bool packed = packed_blk && cl == 0;
-        cT<T> tv[P];
-#pragma unroll
-        for (int m = 0; m < P; ++m) tv[m] = tn[m];
         if (PIPE && u + 1 < u1) load_spec(pn);
         if (k != cur_k || cb != cur_cb || q != cur_q) {
             // R^ of this column: FFT_y of the packed row-pass output of the data
@@ -606,6 +613,13 @@ k_cols_tr_mac(ColJobs jobs, const cT<T>* __restrict__ tw)
             }
         }
         fft_line<T, N, +1, false, ColTwiddles<T, N>>(v, xl, twl, t);
+        // the next unit's spectra, taken before this unit's stores so that
+        // waiting for them does not wait for the stores
+        if (PIPE) {
+            wait_vmem();
+#pragma unroll
+            for (int m = 0; m < P; ++m) tv[m] = tn[m];
+        }
         if (ok) {
             cT<T>* zs = (cT<T>*)J.b + ((int64_t)q * J.nl + l) * J.ncols * J.ldb;
 #pragma unroll

@@ -123,6 +123,13 @@ template <typename V> __device__ __forceinline__ void buf_store(const V& v, __am
 }
 constexpr int64_t BUF_MAX_BYTES = int64_t(1) << 31;
 
+// Wait until every vector memory operation this wavefront has issued so far
+// is complete (s_waitcnt vmcnt(0); the LDS and export counters are left
+// alone).  Placed after a prefetch has had time to arrive and before a
+// batch of stores, it keeps the later wait for the prefetched registers
+// from also waiting for those stores.
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // grid of a persistent launch over `total` work units (at most the blocks
 // resident at once, and at most the test hook's cap when one is set)
 static inline int persistent_grid(int total, int resident)

@@ -158,6 +158,13 @@ k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
             lds_barrier();
 #pragma unroll
             for (int m = 0; m < P; ++m) lds[pr * C::ZR + t + m * TPL] = v[m];
+            // v is free: take the next group's rows now, before this group's
+            // stores, so that waiting for them does not wait for the stores
+            if (PIPE) {
+                wait_vmem();
+#pragma unroll
+                for (int m = 0; m < P; ++m) v[m] = vn[m];
+            }
             lds_barrier();
 #pragma unroll
             for (int i = 0; i < (C::HALF * C::PAIRS) / C::THREADS; ++i) {
@@ -220,9 +227,11 @@ k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
                 if (row0 + rr < J.nrows) dst[pidx(kx, row0 + rr, C::HALF)] = lds[kx * C::SROW + rr];
             }
         }
+        if constexpr (sizeof(T) != 4) {
 #pragma unroll
-        for (int m = 0; m < P; ++m)
-            if (PIPE) v[m] = vn[m];
+            for (int m = 0; m < P; ++m)
+                if (PIPE) v[m] = vn[m];
+        }
     }
 }
 
