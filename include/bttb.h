@@ -348,12 +348,15 @@ bttb_status bttb_batch_query(bttb_batch_t batch, size_t* workspace_bytes);
 
 /* Enqueue the products of every problem on `stream` as one graph launch.
  * io: host array of nplans entries.  Errors: NULL_POINTER, INVALID_VALUE,
- * WORKSPACE_TOO_SMALL, HIP.  Calls on one batch must not overlap. */
+ * WORKSPACE_TOO_SMALL, HIP.  Calls on one batch must not overlap.  A call
+ * with other pointers or counts than the previous one captures a new graph
+ * and first waits for the previous launch to finish. */
 bttb_status bttb_batch_run(bttb_batch_t batch, const bttb_batch_io* io, void* workspace,
                            size_t ws_bytes, void* stream);
 
 /* Release the graph, the capture streams and events and the batch (NULL
- * accepted). */
+ * accepted).  Waits for the batch's last launch to finish first, so a batch
+ * may be destroyed right after bttb_batch_run returns. */
 bttb_status bttb_batch_destroy(bttb_batch_t batch);
 
 /* ------------------------------------------------------------------------

@@ -1153,6 +1153,8 @@ struct bttb_batch_s {
     hipEvent_t ev[kBatchBranches + 1] = {};     // fork and join events
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;      // recorded after each launch of exec
+    bool launched = false;
     std::vector<uintptr_t> key;     // pointers and counts of the captured run
 };
 
@@ -1160,6 +1162,10 @@ namespace {
 
 void batch_release_graph(bttb_batch_s* B)
 {
+    // the last launch of the executable graph may still be running (the
+    // call returns once it is enqueued): wait for it before destroying it
+    if (B->exec && B->launched && B->done) (void)hipEventSynchronize(B->done);
+    B->launched = false;
     if (B->exec) (void)hipGraphExecDestroy(B->exec);
     if (B->graph) (void)hipGraphDestroy(B->graph);
     B->exec = nullptr;
@@ -1262,6 +1268,7 @@ bttb_status bttb_batch_create(const bttb_plan_t* plans, int32_t nplans, int32_t 
             st = hip_check(hipStreamCreateWithFlags(&B->side[b], hipStreamNonBlocking), "stream create");
         for (int b = 0; b <= kBatchBranches && st == BTTB_OK; ++b)
             st = hip_check(hipEventCreateWithFlags(&B->ev[b], hipEventDisableTiming), "event create");
+        if (st == BTTB_OK) st = hip_check(hipEventCreateWithFlags(&B->done, hipEventDisableTiming), "event create");
         if (st != BTTB_OK) { bttb_batch_destroy(B); return st; }
         *out = B;
         return BTTB_OK;
@@ -1317,7 +1324,10 @@ bttb_status bttb_batch_run(bttb_batch_t B, const bttb_batch_io* io, void* worksp
             }
             B->key = key;
         }
-        return hip_check(hipGraphLaunch(B->exec, (hipStream_t)stream), "graph launch");
+        bttb_status st = hip_check(hipGraphLaunch(B->exec, (hipStream_t)stream), "graph launch");
+        if (st != BTTB_OK) return st;
+        B->launched = true;
+        return hip_check(hipEventRecord(B->done, (hipStream_t)stream), "event record");
     } catch (...) {
         return fail(BTTB_ERR_INTERNAL, "unexpected exception in bttb_batch_run");
     }
@@ -1332,6 +1342,7 @@ bttb_status bttb_batch_destroy(bttb_batch_t B)
         if (B->side[b]) (void)hipStreamDestroy(B->side[b]);
     for (int b = 0; b <= kBatchBranches; ++b)
         if (B->ev[b]) (void)hipEventDestroy(B->ev[b]);
+    if (B->done) (void)hipEventDestroy(B->done);
     delete B;
     return BTTB_OK;
 }

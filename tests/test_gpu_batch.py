@@ -135,6 +135,31 @@ def test_batch_partial_products_and_rhs_counts(torch_cuda):
     assert rel_l2(mts[2].cpu().numpy().reshape(3, -1), rs[2].cpu().numpy().reshape(3, -1) @ G2) <= 1e-12
 
 
+def test_batch_destroyed_right_after_run(torch_cuda):
+    """A batch released while its graph launch may still be running (a
+    temporary Batch: the last reference goes when run() returns) waits for
+    that launch, so its outputs are complete: the transposes equal the
+    single calls bit for bit, the forwards to the regrouping of their depth
+    sums (as in the 48-instance test)."""
+    from paper_1912_06976_amd import Batch, Plan
+    torch = torch_cuda
+    plans = [Plan(p, "fp32").generate() for p in W.batch48()[:6]]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(91)
+    ms = [torch.randn((p.nz, p.ny, p.nx), generator=g, device="cuda") for p in plans]
+    rs = [torch.randn((p.sy, p.sx), generator=g, device="cuda") for p in plans]
+    d_ref = [p.forward(m) for p, m in zip(plans, ms)]
+    mt_ref = [p.transpose(r) for p, r in zip(plans, rs)]
+    torch.cuda.synchronize()
+    for k in range(2):
+        ds, mts = Batch(plans).run(ms, rs)   # the batch is released here
+        torch.cuda.synchronize()
+        for i in range(len(plans)):
+            assert rel_l2(ds[i].double().cpu().numpy().reshape(1, -1),
+                          d_ref[i].double().cpu().numpy().reshape(1, -1)) <= 1e-6, "forward %d, run %d" % (i, k)
+            assert torch.equal(mts[i], mt_ref[i]), "transpose %d, run %d" % (i, k)
+
+
 def test_batch_rejects_mixed_precision_and_bad_io(torch_cuda):
     torch = torch_cuda
     from paper_1912_06976_amd import Batch, BttbError, Plan
