@@ -317,8 +317,13 @@ k_rows_c2r(RowJobs jobs, const cT<T>* __restrict__ tw)
         const uint32_t ska = ra < J.nrows ? 0u : BUF_SKIP, skb = rb < J.nrows ? 0u : BUF_SKIP;
         const uint32_t oa0 = (uint32_t)((int64_t)ra * J.out_ld * (int64_t)sizeof(T));
         const uint32_t ld = (uint32_t)(J.out_ld * (int64_t)sizeof(T));
+        // rows that end within the first half of the transform issue no
+        // stores for the second half (a uniform branch: the stores of the
+        // first half stay unconditional, so the wait stays countable)
+        const bool half = J.nv <= N / 2;
 #pragma unroll
         for (int m = 0; m < P; ++m) {
+            if (m >= P / 2 && half) continue;
             const int x = t + m * TPL;
             const uint32_t oa = oa0 + (uint32_t)x * (uint32_t)sizeof(T), skx = x < J.nv ? 0u : BUF_SKIP;
             buf_store(v[m].x, rs, oa | ska | skx);
