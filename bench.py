@@ -131,10 +131,23 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def counter_traffic(kernel):
+# the library's kernel configuration for this workload when the descriptor
+# leaves the tuning fields at 0 (row tile 4, column tile 1, no layer chunks)
+DEFAULT_KERNEL_CONFIG = {"layer_chunk": 0, "row_tile": 4, "col_tile": 1}
+
+
+def effective_kernel_config(pr):
+    return {"layer_chunk": int(pr.get("layer_chunk", 0) or 0),
+            "row_tile": int(pr.get("row_tile", 0) or DEFAULT_KERNEL_CONFIG["row_tile"]),
+            "col_tile": int(pr.get("col_tile", 0) or DEFAULT_KERNEL_CONFIG["col_tile"])}
+
+
+def counter_traffic(kernel, config=None):
     """Scaled HBM bytes (FETCH_SIZE + WRITE_SIZE, rocprofv3 PMC runs) of one
     launch of `kernel`, from the committed profile summary -- only if the
-    kernel sources are unchanged since the counters were taken, else None."""
+    kernel sources are unchanged since the counters were taken and the run's
+    kernel configuration (layer chunks change the launches) is the one they
+    were taken with, else None."""
     import re
     path = os.path.join(ROOT, "profiles", "hbm_counters_gravity_1024_fp32.md")
     if not os.path.exists(path):
@@ -144,6 +157,8 @@ def counter_traffic(kernel):
         return None
     info = json.loads(m.group(1))
     if kernel_source_hash() != info.get("source_sha256"):
+        return None
+    if config is not None and info.get("kernel_config") != config:
         return None
     k = info.get("kernels", {}).get(kernel)
     return None if k is None else k["read_bytes"] + k["write_bytes"]
@@ -442,7 +457,8 @@ def main():
     use_alu = alu["frac"] > hbm["frac"]
     main_r, other = (alu, hbm) if use_alu else (hbm, alu)
     roof = {"bound": "alu" if use_alu else "hbm", "kernel": dom, **main_r,
-            "traffic": counter_traffic(dom), "algorithmic_bytes": kb[dom], "algorithmic_flops": kf[dom],
+            "traffic": counter_traffic(dom, effective_kernel_config(pr)),
+            "algorithmic_bytes": kb[dom], "algorithmic_flops": kf[dom],
             "avg_ms": round(kern[dom], 4),
             ("hbm" if use_alu else "alu"): other,
             "alu_frac_vs_packed_fp32_peak": round(kf[dom] / t_dom / 1e12 / VALU_PEAK_PACKED_TFLOPS, 4)}

@@ -372,8 +372,12 @@ bttb_status bttb_batch_destroy(bttb_batch_t batch);
  * row_tile, col_tile, layer_chunk).  Each candidate runs one forward and one
  * transpose product on seeded uniform inputs, once untimed and then 5 timed
  * times, and counts its fastest time; the plan's default configuration is
- * timed first and another candidate replaces the best so far only when it is
- * at least 2 % faster.  The lengths change the products only by rounding.
+ * timed first (after at least 200 ms of untimed products on it, while the
+ * device's clocks come up) and another candidate replaces the best so far
+ * only when it is at least 2 % faster.  A winner of the default lengths
+ * other than the default configuration is then timed 5 more times
+ * alternately with the default and kept only if it is again at least 2 %
+ * faster.  The lengths change the products only by rounding.
  * Results are cached in a text file (path: environment variable
  * BTTB_TUNE_CACHE, default $HOME/.cache/bttb_autotune.txt), keyed by the
  * shape, precision, accumulation, nrhs and device; a cached key is returned
@@ -385,10 +389,12 @@ bttb_status bttb_autotune(const bttb_problem_desc* desc, int32_t nrhs, void* scr
                           void* stream, bttb_problem_desc* tuned, float* best_ms);
 
 /* Profiling hooks: the same work as bttb_forward / bttb_transpose, with HIP
- * events recorded on the stream around each of the three kernels (row
- * transform, column transform with the depth multiply-accumulate, output row
- * transform); waits for the events and stores the three kernel durations in
- * milliseconds in kernel_ms[0..2].  Synchronises the stream. */
+ * events recorded on the stream around every launch of each of the three
+ * stages (row transform; column transform with the depth multiply-accumulate
+ * and, for a split depth sum, its finishing kernel; output row transform);
+ * waits for the events and stores each stage's summed duration in
+ * milliseconds in kernel_ms[0..2] (with layer chunks the transpose runs the
+ * column and output row stages once per chunk).  Synchronises the stream. */
 bttb_status bttb_forward_profiled(bttb_plan_t plan, const void* spectra, const void* m, void* d,
                                   int32_t nrhs, void* workspace, size_t ws_bytes, void* stream,
                                   float* kernel_ms);

@@ -61,3 +61,21 @@ def test_kernel_source_hash_ignores_comments(tmp_path, monkeypatch):
     assert bench.kernel_source_hash() == h0
     (copy / "kern_common.h").write_text((copy / "kern_common.h").read_text() + "\nint changed_code;\n")
     assert bench.kernel_source_hash() != h0
+
+
+def test_traffic_needs_the_counters_kernel_config(tmp_path, monkeypatch):
+    """Counter bytes are per launch of one kernel configuration: a run with
+    layer chunks (other launches) gets no traffic figure."""
+    import json
+    import bench
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    info = {"source_sha256": bench.kernel_source_hash(), "kernel_config": bench.DEFAULT_KERNEL_CONFIG,
+            "kernels": {"tr_cols_fft_mac": {"read_bytes": 5, "write_bytes": 7}}}
+    (prof / "hbm_counters_gravity_1024_fp32.md").write_text("<!-- traffic-json: %s -->\n" % json.dumps(info))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: info["source_sha256"])
+    assert bench.counter_traffic("tr_cols_fft_mac", bench.effective_kernel_config({})) == 12
+    assert bench.counter_traffic("tr_cols_fft_mac", bench.effective_kernel_config({"layer_chunk": 32})) is None
+    assert bench.counter_traffic("tr_cols_fft_mac", bench.effective_kernel_config({"row_tile": 2})) is None
+    assert bench.counter_traffic("tr_cols_fft_mac", dict(bench.DEFAULT_KERNEL_CONFIG)) == 12
