@@ -212,6 +212,13 @@ k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
                 A[0] = mk<T>(A[0].x, A[P / 2].x);
                 Cc[0] = mk<T>(Cc[0].x, Cc[P / 2].x);
             }
+            // v is free: take the next group's rows before the stores (as
+            // in the FP32 branch)
+            if (PIPE) {
+                wait_vmem();
+#pragma unroll
+                for (int m = 0; m < P; ++m) v[m] = vn[m];
+            }
             lds_barrier();
 #pragma unroll
             for (int m = 0; m < P / 2; ++m) {
@@ -226,11 +233,6 @@ k_rows_r2c(RowJobs jobs, const cT<T>* __restrict__ tw)
                 const int kx = e / C::RT, rr = e % C::RT;
                 if (row0 + rr < J.nrows) dst[pidx(kx, row0 + rr, C::HALF)] = lds[kx * C::SROW + rr];
             }
-        }
-        if constexpr (sizeof(T) != 4) {
-#pragma unroll
-            for (int m = 0; m < P; ++m)
-                if (PIPE) v[m] = vn[m];
         }
     }
 }
